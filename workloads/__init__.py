@@ -1,0 +1,296 @@
+"""Seeded synthetic workloads for the three-bead swimmer step.
+
+This module only *describes* inputs: box shapes, relaxation times, body
+geometry and placement, spring and driving parameters, and the seeded random
+draws of the parameter sweeps.  It holds none of the method's arithmetic, so
+both the CPU oracle and the GPU binding can take their inputs from here without
+sharing any code of the method itself.
+
+Conventions (the paper states none of them in code form):
+
+* D3Q19 lattice, cells ``(i, j, k)`` with ``i`` fastest, linear index
+  ``i + nx*(j + ny*k)``, cell centre ``(i+0.5, j+0.5, k+0.5)``.
+* The swimmer axis is x.  Body order follows the paper's naming of the
+  three-sphere device (Sec. 3.1): index 0 is the middle body B1, index 1 the
+  left body B2 (at -x), index 2 the right body B3 (at +x).
+* Spring rest lengths are centre-to-centre distances (Eq. spring_i).
+* Bead mass follows the paper's design study (Sec. 5.1): 5.44e-13 kg for a
+  4 um sphere in a fluid of density 1360 kg/m^3 gives m = 400 lattice units at
+  r = 4; other radii scale as m = 400 (r/4)^3, and every body of one swimmer
+  gets the same mass (capsules included, as in Sec. 5.1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+SPHERE, CAPSULE, SLAB = 0, 1, 2
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+
+
+@dataclass
+class Body:
+    shape: int = SPHERE
+    radius: float = 3.0
+    half_len: float = 0.0          # capsule: half the cylinder length
+    mass: float = 1.0
+    inertia: Tuple[float, float, float] = (1.0, 1.0, 1.0)  # body frame, axis = local x
+    anchor: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # fixed reference position
+    disp: Tuple[float, float, float] = (0.0, 0.0, 0.0)     # displacement from anchor
+    quat: Tuple[float, float, float, float] = (1.0, 0.0, 0.0, 0.0)  # (w, x, y, z)
+    vel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    omega: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    kinematic: bool = False        # prescribed V and Omega (infinite mass)
+
+
+@dataclass
+class Spring:
+    i: int
+    j: int
+    k: float
+    gamma: float
+    rest_len: float                # centre-to-centre
+
+
+@dataclass
+class Drive:
+    left: int
+    middle: int
+    right: int
+    amplitude: float
+    period: float
+    phase_lag: float               # radians; the right body's force lags by this
+    gate_lagged: bool = False      # right-body force held at 0 until omega*t >= phase_lag
+    off_left: int = -1             # step from which the left force is switched off (-1: never)
+    off_right: int = -1            # step from which the right force is switched off
+
+
+@dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    periodic: Tuple[bool, bool, bool] = (True, False, False)
+    bodies: List[Body] = field(default_factory=list)
+    springs: List[Spring] = field(default_factory=list)
+    drives: List[Drive] = field(default_factory=list)
+    steps: int = 0
+    storage: str = "f64"
+    shift_log2: int = 0
+    note: str = ""
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def to_json(self) -> str:
+        return json.dumps(dataclasses.asdict(self), sort_keys=True)
+
+
+def bead_mass(r: float) -> float:
+    """Bead mass in lattice units, m = 400 (r/4)^3 (design-study density)."""
+    return 400.0 * (r / 4.0) ** 3
+
+
+def sphere_inertia(m: float, r: float) -> Tuple[float, float, float]:
+    i = 0.4 * m * r * r
+    return (i, i, i)
+
+
+def capsule_inertia(m: float, r: float, h: float) -> Tuple[float, float, float]:
+    """Uniform solid capsule (cylinder of length 2h plus two hemispherical caps)
+    of total mass m; returns (axial, transverse, transverse)."""
+    vc = math.pi * r * r * 2.0 * h
+    vs = 4.0 / 3.0 * math.pi * r ** 3
+    mc = m * vc / (vc + vs)
+    ms = m * vs / (vc + vs)
+    H = 2.0 * h
+    ia = mc * r * r / 2.0 + ms * 2.0 * r * r / 5.0
+    it = mc * (H * H / 12.0 + r * r / 4.0) + ms * (2.0 * r * r / 5.0 + H * H / 4.0 + 3.0 * H * r / 8.0)
+    return (ia, it, it)
+
+
+def make_body(shape: int, r: float, m: float, pos, h: float = 0.0, **kw) -> Body:
+    inertia = sphere_inertia(m, r) if shape == SPHERE else capsule_inertia(m, r, h)
+    return Body(shape=shape, radius=float(r), half_len=float(h), mass=float(m),
+                inertia=inertia, anchor=tuple(float(v) for v in pos), **kw)
+
+
+def swimmer(centre, shapes=(SPHERE, SPHERE, SPHERE), r: float = 3.0, h: float = 0.0,
+            l0: Tuple[float, float] = (10.0, 10.0), k: float = 0.05, gamma: float = 0.01,
+            mass: Optional[float] = None, amplitude: float = 2e-4, period: float = 200.0,
+            phase_lag: float = math.pi / 2, base: int = 0, **drive_kw):
+    """Three bodies on the x axis, middle body at ``centre``.
+
+    ``shapes`` lists (middle, left, right); ``l0`` = (left arm, right arm)
+    centre-to-centre rest lengths.  Returns (bodies, springs, drive); body
+    indices are offset by ``base`` so several swimmers can share one box."""
+    m = bead_mass(r) if mass is None else mass
+    cx, cy, cz = centre
+    hm, hl, hr = [(h if s == CAPSULE else 0.0) for s in shapes]
+    bodies = [
+        make_body(shapes[0], r, m, (cx, cy, cz), hm),
+        make_body(shapes[1], r, m, (cx - l0[0], cy, cz), hl),
+        make_body(shapes[2], r, m, (cx + l0[1], cy, cz), hr),
+    ]
+    springs = [Spring(base + 1, base + 0, k, gamma, l0[0]),
+               Spring(base + 2, base + 0, k, gamma, l0[1])]
+    drive = Drive(left=base + 1, middle=base + 0, right=base + 2, amplitude=amplitude,
+                  period=period, phase_lag=phase_lag, **drive_kw)
+    return bodies, springs, drive
+
+
+# --------------------------------------------------------------------------
+# The five benchmark workloads
+# --------------------------------------------------------------------------
+
+def plain_f64_small() -> Case:
+    """48x32x32, tau 1, r=3 three-sphere swimmer, 400 steps, FP64 (seed 0, nothing drawn)."""
+    b, s, d = swimmer((24.0, 16.0, 16.0), r=3.0, l0=(10.0, 10.0), k=0.05, gamma=0.01,
+                      amplitude=2e-4, period=200.0, phase_lag=math.pi / 2)
+    return Case("plain_f64_48x32x32", 48, 32, 32, 1.0, bodies=b, springs=s, drives=[d],
+                steps=400, storage="f64")
+
+
+def plain_at_scale(storage: str = "f32", seed: int = 0, periods: int = 20) -> Case:
+    """256x128x128, tau 0.8, r=6 swimmer, rest length 24, amplitude ~ U[1e-4,5e-4]."""
+    rng = np.random.default_rng(seed)
+    a = float(rng.uniform(1e-4, 5e-4))
+    b, s, d = swimmer((128.0, 64.0, 64.0), r=6.0, l0=(24.0, 24.0), k=0.05, gamma=0.01,
+                      amplitude=a, period=1000.0, phase_lag=math.pi / 2)
+    return Case("plain_256x128x128", 256, 128, 128, 0.8, bodies=b, springs=s, drives=[d],
+                steps=periods * 1000, storage=storage)
+
+
+def capsule_swimmer(nx: int, ny: int, nz: int, design: str = "SCS", storage: str = "f32",
+                    steps: int = 5000, shift_log2: int = 16) -> Case:
+    """Capsule variant: r=5 bodies, capsules with cylinder length 10 parallel to x,
+    surface gap 10 between neighbours; ``design`` is 'SCS' or 'CCC' (middle is
+    the second letter)."""
+    r, h, gap = 5.0, 5.0, 10.0
+    kinds = {"S": SPHERE, "C": CAPSULE}
+    left, mid, right = (kinds[c] for c in design)
+    ext = {SPHERE: r, CAPSULE: r + h}
+    l_left = ext[left] + ext[mid] + gap
+    l_right = ext[right] + ext[mid] + gap
+    b, s, d = swimmer((nx / 2.0, ny / 2.0, nz / 2.0), shapes=(mid, left, right), r=r, h=h,
+                      l0=(l_left, l_right), k=0.05, gamma=0.01, mass=bead_mass(r),
+                      amplitude=3e-4, period=1000.0, phase_lag=math.pi / 2)
+    return Case(f"capsule_{design}_{nx}x{ny}x{nz}", nx, ny, nz, 0.7, bodies=b, springs=s,
+                drives=[d], steps=steps, storage=storage, shift_log2=shift_log2)
+
+
+def capsule_full(design: str = "SCS", storage: str = "f32") -> Case:
+    return capsule_swimmer(512, 256, 256, design, storage, steps=5000)
+
+
+def capsule_crop(design: str = "SCS", storage: str = "f32") -> Case:
+    return capsule_swimmer(128, 64, 64, design, storage, steps=1000)
+
+
+def batched_sweep(seed: int = 7, n: int = 96, periods: int = 10, storage: str = "f32") -> List[Case]:
+    """96 independent C1-type swimmers with per-swimmer draws, in this order:
+    (nx, ny, nz, tau, amplitude, period, phase lag)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        nx = int(rng.choice([96, 128, 160]))
+        ny = int(rng.choice([48, 64]))
+        nz = int(rng.choice([48, 64]))
+        tau = float(rng.uniform(0.6, 1.2))
+        a = float(rng.uniform(1e-4, 5e-4))
+        T = int(rng.choice([400, 800, 1200]))
+        psi = float(rng.uniform(0.0, math.pi))
+        b, s, d = swimmer((nx / 2.0, ny / 2.0, nz / 2.0), r=3.0, l0=(10.0, 10.0), k=0.05,
+                          gamma=0.01, amplitude=a, period=float(T), phase_lag=psi)
+        out.append(Case(f"sweep{q:02d}_{nx}x{ny}x{nz}", nx, ny, nz, tau, bodies=b, springs=s,
+                        drives=[d], steps=periods * T, storage=storage))
+    return out
+
+
+def adjoint_case(storage: str = "f32", periods: int = 2) -> Case:
+    """128x64x64, tau 0.9, r=4 swimmer, l0=16, period 500, two periods."""
+    b, s, d = swimmer((64.0, 32.0, 32.0), r=4.0, l0=(16.0, 16.0), k=0.05, gamma=0.01,
+                      amplitude=2e-4, period=500.0, phase_lag=math.pi / 2)
+    return Case("adjoint_128x64x64", 128, 64, 64, 0.9, bodies=b, springs=s, drives=[d],
+                steps=periods * 500, storage=storage)
+
+
+# --------------------------------------------------------------------------
+# Test workloads
+# --------------------------------------------------------------------------
+
+def forced_motion(steps: int = 400, storage: str = "f64") -> Case:
+    """A kinematic sphere (r=4) dragged at V=(0.031, 0.017, 0) lu/step through a
+    64x48x48 channel: it crosses about a dozen cells, so cells are covered and
+    uncovered (refilled) throughout the run."""
+    body = make_body(SPHERE, 4.0, bead_mass(4.0), (20.0, 17.0, 24.0),
+                     vel=(0.031, 0.017, 0.0), kinematic=True)
+    return Case("forced_motion_64x48x48", 64, 48, 48, 0.8, bodies=[body], steps=steps,
+                storage=storage)
+
+
+def random_small(seed: int, storage: str = "f64") -> Case:
+    """A small random box with one to three free or kinematic spheres/capsules,
+    placed without overlap and away from the walls; used for property tests."""
+    rng = np.random.default_rng(1000 + seed)
+    nx = int(rng.integers(12, 29))
+    ny = int(rng.integers(12, 25))
+    nz = int(rng.integers(12, 25))
+    periodic = (True, bool(rng.integers(0, 2)), False)
+    tau = float(rng.uniform(0.55, 1.6))
+    nb = int(rng.integers(1, 4))
+    bodies: List[Body] = []
+    tries = 0
+    while len(bodies) < nb and tries < 200:
+        tries += 1
+        shape = int(rng.integers(0, 2))
+        r = float(rng.uniform(1.2, 3.0))
+        h = float(rng.uniform(0.5, 2.5)) if shape == CAPSULE else 0.0
+        ext = r + h
+        lo = [ext + 1.5] * 3
+        hi = [nx - ext - 1.5, ny - ext - 1.5, nz - ext - 1.5]
+        if any(h_ <= l_ for l_, h_ in zip(lo, hi)):
+            continue
+        pos = [float(rng.uniform(l_, h_)) for l_, h_ in zip(lo, hi)]
+        ok = True
+        for other in bodies:
+            d = math.dist(pos, other.anchor)
+            if d < ext + other.radius + other.half_len + 2.5:
+                ok = False
+        if not ok:
+            continue
+        kin = bool(rng.integers(0, 2))
+        vel = tuple(float(v) for v in rng.uniform(-0.02, 0.02, 3)) if kin else (0.0, 0.0, 0.0)
+        omg = tuple(float(v) for v in rng.uniform(-0.01, 0.01, 3)) if kin else (0.0, 0.0, 0.0)
+        ang = float(rng.uniform(0, math.pi))
+        ax = rng.normal(size=3)
+        ax = ax / np.linalg.norm(ax)
+        quat = (math.cos(ang / 2),) + tuple(float(v) * math.sin(ang / 2) for v in ax)
+        m = bead_mass(r)
+        b = make_body(shape, r, m, pos, h, vel=vel, omega=omg, quat=quat, kinematic=kin)
+        bodies.append(b)
+    springs: List[Spring] = []
+    drives: List[Drive] = []
+    if len(bodies) == 3:
+        springs = [Spring(1, 0, 0.05, 0.01, math.dist(bodies[1].anchor, bodies[0].anchor)),
+                   Spring(2, 0, 0.05, 0.01, math.dist(bodies[2].anchor, bodies[0].anchor))]
+        drives = [Drive(1, 0, 2, 1e-3, 40.0, float(rng.uniform(0, math.pi)))]
+    return Case(f"random{seed}_{nx}x{ny}x{nz}", nx, ny, nz, tau, periodic=periodic,
+                bodies=bodies, springs=springs, drives=drives, steps=int(rng.integers(8, 30)),
+                storage=storage)
+
+
+def initial_populations(case: Case, seed: int, amp: float = 1e-3) -> np.ndarray:
+    """Seeded random deviations dF (shape [19, nz, ny, nx], float64) for tests that
+    start from a perturbed state; bodies' cells are left as given (the method
+    discards populations inside bodies)."""
+    rng = np.random.default_rng(seed)
+    return amp * rng.standard_normal((19, case.nz, case.ny, case.nx))
