@@ -1,0 +1,216 @@
+/*
+ * lbmswim: the coupled lattice-Boltzmann / rigid-body step for three-bead
+ * swimmers of Pickl et al., arXiv:1108.0786, on one AMD Instinct MI355X (gfx950).
+ *
+ * One call of lbm_step advances every box by the coupled step of Alg. 2
+ * (Sec. 2.3):
+ *   1. the bodies are mapped onto the lattice as moving-boundary cells, cells
+ *      that leave a body are refilled with equilibrium populations, cells that
+ *      enter one are dropped (Sec. 2.3, flag changes);
+ *   2. every fluid cell is collided with LBGK (Sec. 2.1, Eqs. lbgk, collide) and
+ *      streamed (Eq. streaming), with halfway bounce-back at the channel walls
+ *      (Eq. lbm:bounce_back) and moving bounce-back at body cells (Sec. 2.3);
+ *   3. the momentum-exchange force and torque on every body are summed
+ *      (Eq. hydroF);
+ *   4. the driving forces of Eqs. FB1-FB3 are added;
+ *   5. the rigid bodies take one time step (Alg. 1) with the spring-damper
+ *      forces of Eqs. osci_i/j (total force of Eq. totalFSwimmer).
+ *
+ * Conventions
+ *   - Lattice: D3Q19, directions numbered 0 (rest), 1..6 = +x,-x,+y,-y,+z,-z,
+ *     7..18 = (+x+y),(-x-y),(+x-y),(-x+y),(+x+z),(-x-z),(+x-z),(-x+z),
+ *     (+y+z),(-y-z),(+y-z),(-y+z); weights 1/3, 1/18, 1/36.
+ *   - Cells (i,j,k), i fastest, linear index i + nx*(j + ny*k), centre
+ *     (i+1/2, j+1/2, k+1/2).  Non-periodic axes have halfway bounce-back walls
+ *     at coordinates 0 and n.
+ *   - Populations are stored as deviations dF = f - w_alpha from the rest
+ *     weights, structure of arrays: element [alpha][k][j][i] at
+ *     alpha*N + cell, N = nx*ny*nz.  Storage LBM_F64 and LBM_F32 hold dF;
+ *     LBM_F16S and LBM_BF16S hold dF * 2^shift_log2 in IEEE half / bfloat16.
+ *     LBM_F64 collides in double, the others in float; forces, torques and the
+ *     rigid-body state are always double.
+ *   - Flags, one byte per cell: low 7 bits 0 = fluid, 1+b = inside body b;
+ *     bit 7 is set on fluid cells that have at least one D3Q19 neighbour inside
+ *     a body (the cells that own boundary links).
+ *   - A body is inside-tested at cell centres exactly in this float64
+ *     sequence (no fused multiply-add): X = anchor + disp; R = floor(X);
+ *     f = X - R; d = cell index - R (integer, wrapped into [-L/2, L - L/2) on
+ *     periodic axes); r = (d + 0.5) - f; sphere: (rx*rx + ry*ry) + rz*rz <= rad*rad;
+ *     capsule (axis a = body-frame x rotated by quat): t = clamp((rx*ax + ry*ay)
+ *     + rz*az, -h, h), s = r - t*a, (sx*sx + sy*sy) + sz*sz <= rad*rad.
+ *   - Boundary links are (fluid cell, direction alpha pointing into the body,
+ *     body index), sorted by (cell, alpha).
+ *
+ * Memory ownership: population, flag and trajectory buffers are device
+ * memory owned by the caller and never freed by the library.  The context
+ * and its scratch (link lists, body tables, per-cell link offsets) belong to
+ * the library and are released by lbm_destroy.  Host structures passed in are
+ * copied before the call returns.
+ *
+ * Ordering: calls are enqueued on the stream given in lbm_params and return
+ * without waiting, except the ones documented as synchronising.  A context
+ * must not be used from two threads at once.
+ *
+ * Errors: every function returns LBM_OK or a negative code; nothing aborts.
+ * After LBM_E_HIP the context is poisoned and only lbm_last_error and
+ * lbm_destroy may be called.  lbm_last_error describes the last failure.
+ */
+#ifndef LBMSWIM_H
+#define LBMSWIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,       /* invalid argument or configuration */
+    LBM_E_HIP = -2,       /* HIP runtime error; context poisoned */
+    LBM_E_OVERLAP = -3,   /* bodies overlap each other or a wall */
+    LBM_E_UNSTABLE = -4,  /* a body force or state became non-finite */
+    LBM_E_STATE = -5,     /* call not valid in the current state */
+    LBM_E_CAPACITY = -6   /* link list exceeded its capacity */
+};
+
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
+enum { LBM_SPHERE = 0, LBM_CAPSULE = 1 };
+
+/* doubles per body per step in the trajectory record:
+ * disp[3], vel[3], omega[3], F_hydro[3], T_hydro[3], step */
+#define LBM_TRAJ_DOUBLES 16
+
+/* One box.  tau > 0.5 is the LBGK relaxation time in units of the time step
+ * (Eq. lbgk).  pop[0] holds the initial deviations (the caller fills it;
+ * zero is the fluid at rest); pop[1] is the second buffer of the two-buffer
+ * sweep.  traj (optional, may be NULL) receives LBM_TRAJ_DOUBLES * nb
+ * doubles per step at record (step % traj_cap). */
+typedef struct {
+    int32_t nx, ny, nz;
+    uint32_t periodic_mask;   /* bit 0 = x, bit 1 = y, bit 2 = z */
+    double tau;
+    int32_t storage;          /* LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S */
+    int32_t shift_log2;       /* scale exponent of LBM_F16S / LBM_BF16S */
+    void *pop[2];             /* device, 19*N elements of the storage type each */
+    uint8_t *flags;           /* device, N bytes; cleared by lbm_init */
+    double *traj;             /* device, optional */
+    int64_t traj_cap;         /* records in traj */
+    void *stream;             /* hipStream_t; all work of the context goes here */
+} lbm_params;
+
+/* A rigid body (Sec. 2.2).  Positions are anchor + disp; disp accumulates
+ * the motion so that small displacements keep full precision.  quat =
+ * (w, x, y, z) rotates the body frame, whose x axis is a capsule's axis.
+ * inertia holds the principal moments in the body frame.  kinematic bodies
+ * keep their prescribed vel and omega (infinitely heavy). */
+typedef struct {
+    int32_t shape;            /* LBM_SPHERE or LBM_CAPSULE */
+    int32_t kinematic;
+    double radius, half_len;  /* half_len: half the cylinder length of a capsule */
+    double mass, inertia[3];
+    double anchor[3], disp[3], quat[4], vel[3], omega[3];
+} lbm_body;
+
+/* Damped spring between bodies i and j (Eqs. spring_i, damp_i, osci_i/j):
+ * with d = x_i - x_j, body i feels -k (|d| - rest_len) d/|d| - gamma (u_i - u_j)
+ * and body j the opposite; rest_len is the centre-to-centre rest length. */
+typedef struct {
+    int32_t i, j;
+    double k, gamma, rest_len;
+} lbm_spring;
+
+/* Driving protocol of Eqs. FB1-FB3 along x at step t, omega = 2 pi / period:
+ * left body -a sin(omega t), right body a sin(omega t - phase_lag), middle
+ * body minus their sum.  gate_lagged holds the right force at zero while
+ * omega t < phase_lag; off_left / off_right (-1 = never) switch the left /
+ * right force off from that step on. */
+typedef struct {
+    int32_t left, middle, right, gate_lagged;
+    double amplitude, period, phase_lag;
+    int64_t off_left, off_right;
+} lbm_drive;
+
+/* Create a context for one box.  Validates the parameters (LBM_E_ARG),
+ * allocates the library's scratch and clears params->flags. */
+int lbm_init(const lbm_params *params, lbm_ctx **out);
+
+/* Create a context for nbox independent boxes that are stepped together by
+ * single launches (parameter sweeps).  All boxes must share one storage type
+ * and params[0].stream.  Box b is addressed by the *_box calls. */
+int lbm_init_batch(const lbm_params *params, int32_t nbox, lbm_ctx **out);
+
+/* Set the bodies, springs and driving protocols of box 0 (lbm_set_bodies)
+ * or of box `box`, and map them onto the lattice (Sec. 2.3).  Bodies must not
+ * overlap each other or reach a wall (LBM_E_OVERLAP); indices must be in
+ * range (LBM_E_ARG).  On a box that already holds bodies, cells that leave a
+ * body are refilled as in a step. */
+int lbm_set_bodies(lbm_ctx *ctx, const lbm_body *bodies, int32_t nb,
+                   const lbm_spring *springs, int32_t ns,
+                   const lbm_drive *drives, int32_t nd);
+int lbm_set_bodies_box(lbm_ctx *ctx, int32_t box, const lbm_body *bodies, int32_t nb,
+                       const lbm_spring *springs, int32_t ns,
+                       const lbm_drive *drives, int32_t nd);
+
+/* Stop box `box` once it has taken max_steps steps (-1: no limit).  Boxes
+ * that reached their limit are left out of later launches. */
+int lbm_set_step_limit(lbm_ctx *ctx, int32_t box, int64_t max_steps);
+
+/* Advance every box that has not reached its limit by nsteps coupled steps
+ * (Alg. 2), asynchronously on the context's stream. */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Hydrodynamic force and torque on every body from the last step
+ * (Eq. hydroF), nb x 3 doubles each.  on_device = 1: F and T are device
+ * pointers and the copy is enqueued; on_device = 0: host pointers and the
+ * call synchronises the stream. */
+int lbm_body_forces(lbm_ctx *ctx, double *F, double *T, int32_t on_device);
+int lbm_body_forces_box(lbm_ctx *ctx, int32_t box, double *F, double *T, int32_t on_device);
+
+/* Copy the current body states into out[0..nb) (host).  Synchronising. */
+int lbm_get_bodies(lbm_ctx *ctx, lbm_body *out, int32_t nb);
+int lbm_get_bodies_box(lbm_ctx *ctx, int32_t box, lbm_body *out, int32_t nb);
+
+/* Copy box `box`'s boundary links into host arrays of capacity cap; *n gets
+ * the number of links (LBM_E_CAPACITY if cap is too small).  Synchronising. */
+int lbm_get_links(lbm_ctx *ctx, int32_t box, int32_t *cell, int8_t *dir, int8_t *body,
+                  int64_t cap, int64_t *n);
+
+/* Write box `box`'s current pre-collision deviations dF as double into the
+ * device array dst (19*N, same layout as the populations), zero at body cells. */
+int lbm_export_populations(lbm_ctx *ctx, int32_t box, double *dst);
+
+/* Overwrite box `box`'s current populations from the device array src
+ * (19*N doubles of dF), converting to the storage type. */
+int lbm_import_populations(lbm_ctx *ctx, int32_t box, const double *src);
+
+/* Steps taken by box `box` so far.  Synchronising. */
+int lbm_step_count(lbm_ctx *ctx, int32_t box, int64_t *steps);
+
+/* Synchronise and report a device-side failure: LBM_E_UNSTABLE if a body
+ * force or state became non-finite, LBM_E_CAPACITY if a link list overflowed. */
+int lbm_status(lbm_ctx *ctx);
+
+/* Kernel timing.  With enable = 1, lbm_step records a pair of HIP events
+ * on the context's stream around every sweep launch and every coupling
+ * launch (and keeps them until lbm_get_timing); enable = 0 stops recording
+ * and drops the recorded events.  lbm_get_timing synchronises, and writes the
+ * summed durations in milliseconds and the launch counts since timing was
+ * enabled: out_ms[0] sweep, out_ms[1] coupling; out_n likewise. */
+int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
+int lbm_get_timing(lbm_ctx *ctx, double out_ms[2], int64_t out_n[2]);
+
+/* Write sizeof(lbm_params), sizeof(lbm_body), sizeof(lbm_spring) and
+ * sizeof(lbm_drive) into out[0..3] so that a binding can check its struct
+ * layout.  Touches no device. */
+int lbm_struct_sizes(int64_t out[4]);
+
+const char *lbm_last_error(const lbm_ctx *ctx);
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMSWIM_H */

@@ -84,6 +84,13 @@ class OracleSim:
         self.flags = new
         self.links = coupling.links(new, self.nbr)
 
+    def map_next(self):
+        """Apply the mapping of the next step now (step 1 of Alg. 2 for step n,
+        which the next call of ``step`` would do first and then find nothing to
+        change).  State compared at a step boundary is taken after it."""
+        self.remap()
+        return self
+
     def wall_velocity(self, b, cells):
         return coupling.wall_velocity(self.bodies[b], cells, self.dims, self.periodic)
 

@@ -1,0 +1,130 @@
+// Shared device-side definitions: the D3Q19 velocity set, the storage
+// formats of the population deviations, and the device tables of a box.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D3Q19 (Sec. 2.1): 0 rest; 1..6 axis; 7..18 face diagonals in (d, -d) pairs.
+__host__ __device__ constexpr int ex(int a) {
+    constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[a];
+}
+__host__ __device__ constexpr int ey(int a) {
+    constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[a];
+}
+__host__ __device__ constexpr int ez(int a) {
+    constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[a];
+}
+__host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+__host__ __device__ constexpr double wgt(int a) {
+    return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// 36 * 2 w_alpha: integer weight of the geometric part of the momentum exchange
+__host__ __device__ constexpr int two_w36(int a) { return a == 0 ? 24 : (a <= 6 ? 4 : 2); }
+
+constexpr int kBodyShapeSphere = 0;
+constexpr int kBodyShapeCapsule = 1;
+constexpr uint8_t kNearBit = 0x80;
+constexpr uint8_t kOwnerMask = 0x7f;
+
+// ---------------------------------------------------------------------------
+// Storage formats.  Compute type C is double for double storage, float
+// otherwise.  The 16-bit formats hold dF * 2^s.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+
+template <typename S> struct Storage;
+template <> struct Storage<double> {
+    using C = double;
+    static __device__ __forceinline__ double load(const double *p, size_t i, float) { return p[i]; }
+    static __device__ __forceinline__ void store(double *p, size_t i, double v, float) { p[i] = v; }
+};
+template <> struct Storage<float> {
+    using C = float;
+    static __device__ __forceinline__ float load(const float *p, size_t i, float) { return p[i]; }
+    static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
+};
+template <> struct Storage<_Float16> {
+    using C = float;
+    static __device__ __forceinline__ float load(const _Float16 *p, size_t i, float inv_scale) {
+        return (float)p[i] * inv_scale;
+    }
+    static __device__ __forceinline__ void store(_Float16 *p, size_t i, float v, float scale) {
+        p[i] = (_Float16)(v * scale);
+    }
+};
+__device__ __forceinline__ float bf16_to_float(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+    // round to nearest even; NaN stays NaN
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+template <> struct Storage<bf16_t> {
+    using C = float;
+    static __device__ __forceinline__ float load(const bf16_t *p, size_t i, float inv_scale) {
+        return bf16_to_float(p[i].bits) * inv_scale;
+    }
+    static __device__ __forceinline__ void store(bf16_t *p, size_t i, float v, float scale) {
+        p[i].bits = float_to_bf16(v * scale);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Device tables
+// ---------------------------------------------------------------------------
+struct DevBody {
+    double anchor[3], D[3], V[3], O[3], q[4];
+    double Xmap[3];            // position at the last remap (bounds the remap box)
+    double F[3], T[3];         // hydrodynamic force and torque of the last step
+    double radius, half_len, mass;
+    double inertia[3];         // principal moments, body frame
+    int shape, kinematic;
+};
+
+struct DevSpring {
+    int i, j;
+    double k, gamma, rest_len;
+};
+
+struct DevDrive {
+    int left, middle, right, gate;
+    double amplitude, period, phase_lag;
+    long long off_left, off_right;
+};
+
+struct BoxDesc {
+    int nx, ny, nz, per;       // per: bit 0 x, 1 y, 2 z periodic
+    int N, nb, ns, nd;
+    double omega;              // 1 / tau
+    float omegaf, scale, inv_scale, pad0;
+    void *pop0, *pop1;
+    uint8_t *flags;
+    uint8_t *old_owner;        // N bytes: owner before the last remap
+    int *link_cell;
+    signed char *link_dir, *link_body;
+    double2 *link_val;         // (dF~_alpha(x_f), rho(x_f)) of each link, written by the sweep
+    int *link_base;            // N ints: first link of a boundary cell
+    int link_cap;
+    int pad1;
+    DevBody *bodies;
+    DevSpring *springs;
+    DevDrive *drives;
+    double *traj;
+    long long traj_cap;
+    // mutable state, advanced on the device
+    long long step;
+    int cur;                   // index of the buffer holding the current populations
+    int link_count;
+    int status;                // 0 ok, else an lbm error code
+    int pad2;
+};
+
+}  // namespace lbm

@@ -1,0 +1,184 @@
+"""GPU path (through the C-ABI) against the CPU oracle, element by element.
+
+Metrics (normalised because forces and displacements cross zero):
+  populations   max |dF_gpu - dF_orc| / max |dF_orc| over the box
+  forces        max_n ||F_gpu - F_orc||_inf / max_n ||F_orc||_inf
+  torques       the same, scaled by max ||F_orc|| times the body radius
+  displacement  max_n |D_gpu - D_orc| / max_n |D_orc|
+Flags and boundary links must agree bit for bit.  Tolerances: 1e-12 for
+FP64 storage, 1e-5 for FP32 storage."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleSim
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, **kw):
+    from paper_1108_0786_amd.sim import Sim
+    return Sim(case, device="cuda:0", **kw)
+
+
+def _oracle_traj(orc):
+    F = np.array([t["F"] for t in orc.traj], dtype=float)
+    T = np.array([t["T"] for t in orc.traj], dtype=float)
+    D = np.array([t["D"] for t in orc.traj], dtype=float)
+    return F, T, D
+
+
+def _gpu_traj(sim, steps):
+    tr = sim.trajectory()[:steps]
+    return tr[:, :, 9:12], tr[:, :, 12:15], tr[:, :, 0:3]
+
+
+def _rel(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / scale if scale > 0 else np.abs(a - b).max()
+
+
+def _check_geometry(sim, orc):
+    orc.map_next()  # the library maps step n+1 at the end of step n
+    gf = sim.flags()
+    assert np.array_equal(gf & 0x7F, orc.flags), "flags differ"
+    lc, ld, lb = orc.links
+    near = np.zeros(orc.N, dtype=bool)
+    near[lc] = True
+    assert np.array_equal((gf & 0x80) != 0, near), "near-body marks differ"
+    g = sim.links()
+    assert np.array_equal(g[0], lc) and np.array_equal(g[1], ld) and np.array_equal(g[2], lb), "links differ"
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    case = W.plain_f64_small()
+    orc = OracleSim(case).run(case.steps)
+    return case, orc
+
+
+def test_small_case_geometry_bitexact():
+    case = W.plain_f64_small()
+    print(f"[gpu] geometry {case.name}", flush=True)
+    sim = _sim(case, storage="f64")
+    _check_geometry(sim, OracleSim(case))
+    sim.close()
+
+
+def test_small_case_fp64_parity(c1_oracle):
+    case, orc = c1_oracle
+    print(f"[gpu] fp64 parity {case.name} {case.steps} steps", flush=True)
+    sim = _sim(case, storage="f64", traj_cap=case.steps)
+    sim.step(case.steps)
+    sim.status()
+    _check_geometry(sim, orc)
+    Fo, To, Do = _oracle_traj(orc)
+    Fg, Tg, Dg = _gpu_traj(sim, case.steps)
+    eF = _rel(Fg, Fo)
+    eT = np.abs(Tg - To).max() / (np.abs(Fo).max() * case.bodies[0].radius)
+    eD = _rel(Dg[:, :, 0], Do[:, :, 0])
+    pg, po = sim.populations(), orc.populations()
+    eP = _rel(pg, po)
+    ef = np.abs(pg - po).max() / (1.0 / 3.0 + np.abs(po).max())  # on f = w + dF
+    print(f"[gpu] errors F {eF:.2e} T {eT:.2e} D {eD:.2e} dF {eP:.2e} f {ef:.2e}", flush=True)
+    assert eF < 1e-12 and eT < 1e-12 and eD < 1e-12 and eP < 1e-12
+    sim.close()
+
+
+def test_small_case_fp32_parity(c1_oracle):
+    case, orc = c1_oracle
+    print(f"[gpu] fp32 parity {case.name}", flush=True)
+    sim = _sim(case, storage="f32", traj_cap=case.steps)
+    sim.step(case.steps)
+    sim.status()
+    _check_geometry(sim, orc)
+    Fo, To, Do = _oracle_traj(orc)
+    Fg, Tg, Dg = _gpu_traj(sim, case.steps)
+    eF, eD = _rel(Fg, Fo), _rel(Dg[:, :, 0], Do[:, :, 0])
+    eP = _rel(sim.populations(), orc.populations())
+    print(f"[gpu] fp32 errors F {eF:.2e} D {eD:.2e} dF {eP:.2e}", flush=True)
+    assert eF < 1e-5 and eD < 1e-5 and eP < 1e-4
+    sim.close()
+
+
+def test_forced_motion_remap_parity():
+    # a kinematic sphere crossing cells: cover and uncover (refill) every few steps
+    case = W.forced_motion(steps=80)
+    df0 = W.initial_populations(case, seed=11, amp=1e-4)
+    print(f"[gpu] forced motion {case.name} {case.steps} steps", flush=True)
+    orc = OracleSim(case, df0=df0)
+    sim = _sim(case, storage="f64", traj_cap=case.steps, df0=df0)
+    events = 0
+    for chunk in range(4):
+        before = orc.flags.copy()
+        orc.run(case.steps // 4)
+        sim.step(case.steps // 4)
+        events += int(np.count_nonzero(before != orc.flags))
+        _check_geometry(sim, orc)
+        eP = _rel(sim.populations(), orc.populations())
+        print(f"[gpu] forced motion after {orc.n} steps: dF err {eP:.2e}", flush=True)
+        assert eP < 1e-12, eP
+    Fo, To, Do = _oracle_traj(orc)
+    Fg, Tg, Dg = _gpu_traj(sim, case.steps)
+    eF = _rel(Fg, Fo)
+    print(f"[gpu] forced motion: flag changes {events}, F err {eF:.2e}", flush=True)
+    assert events > 50 and eF < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_small_boxes_fp64(seed):
+    case = W.random_small(seed)
+    df0 = W.initial_populations(case, seed=100 + seed, amp=1e-3)
+    print(f"[gpu] random {case.name} bodies {len(case.bodies)} steps {case.steps}", flush=True)
+    orc = OracleSim(case, df0=df0).run(case.steps)
+    sim = _sim(case, storage="f64", traj_cap=case.steps, df0=df0)
+    sim.step(case.steps)
+    sim.status()
+    _check_geometry(sim, orc)
+    eP = _rel(sim.populations(), orc.populations())
+    Fo, To, Do = _oracle_traj(orc)
+    Fg, Tg, Dg = _gpu_traj(sim, case.steps)
+    eF = _rel(Fg, Fo)
+    eT = np.abs(Tg - To).max() / max(np.abs(To).max(), 1e-300)
+    print(f"[gpu] random errors dF {eP:.2e} F {eF:.2e} T {eT:.2e}", flush=True)
+    assert eP < 1e-12 and eF < 1e-12 and eT < 1e-11
+    sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_rest_state_stays_exactly_zero(storage):
+    case = W.plain_f64_small()
+    case.drives = []
+    print(f"[gpu] rest state {storage}", flush=True)
+    sim = _sim(case, storage=storage, shift_log2=16)
+    sim.step(10)
+    F, T = sim.forces()
+    assert not np.any(sim.populations()) and not np.any(F) and not np.any(T)
+    sim.close()
+
+
+def test_nonfinite_state_is_reported():
+    from paper_1108_0786_amd._abi import LBM_E_UNSTABLE, LbmError
+    case = W.plain_f64_small()
+    df0 = np.zeros((19, case.nz, case.ny, case.nx))
+    df0[:, 16, 16, 20] = np.nan  # a fluid cell next to the middle sphere
+    print("[gpu] non-finite state", flush=True)
+    sim = _sim(case, storage="f64", df0=df0)
+    sim.step(3)
+    with pytest.raises(LbmError) as e:
+        sim.status()
+    assert e.value.code == LBM_E_UNSTABLE
+    sim.close()
+
+
+def test_overlapping_bodies_rejected():
+    from paper_1108_0786_amd._abi import LBM_E_OVERLAP, LbmError
+    case = W.plain_f64_small()
+    case.bodies[1].anchor = (20.0, 16.0, 16.0)  # 4 lu from the middle sphere, r = 3
+    with pytest.raises(LbmError) as e:
+        _sim(case, storage="f64")
+    assert e.value.code == LBM_E_OVERLAP
