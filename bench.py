@@ -79,6 +79,94 @@ def time_leg(case, storage, steps, warmup):
     return out
 
 
+def batched_leg(periods=10):
+    """Parameter sweep: 96 swimmers in their own boxes (seed 7), each advanced
+    10 periods (4000-12000 steps), once as one batched context (one launch per
+    kernel per step for all active boxes, replayed from HIP graphs, launch
+    shapes from the autotuner) and once box after box."""
+    import torch
+
+    import workloads as W
+    from paper_1108_0786_amd import autotune
+    from paper_1108_0786_amd.sim import BatchSim, Sim
+
+    cases = W.batched_sweep(seed=7, periods=periods, storage="f32")
+    lups = sum(c.ncells * c.steps for c in cases)
+    print(f"[bench] batched sweep: {len(cases)} boxes, {sum(c.ncells for c in cases)} cells, "
+          f"{lups:.3e} cell updates", file=sys.stderr, flush=True)
+    scratch = BatchSim(cases, storage="f32")
+    best = autotune.tune(scratch, steps=32)
+    scratch.close()
+    del scratch
+    batch = BatchSim(cases, storage="f32", tune=best)
+    for b, c in enumerate(cases):
+        batch.set_step_limit(b, c.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(max(c.steps for c in cases))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batch.status()
+    disp = [batch.bodies(b)[0]["D"][0] for b in range(len(cases))]
+    batch.close()
+    del batch
+    print(f"[bench] batched: {t_batch:.2f} s ({lups / t_batch / 1e6:.0f} MLUPS), tuning {best}",
+          file=sys.stderr, flush=True)
+    t_seq = 0.0
+    for i, c in enumerate(cases):
+        sim = Sim(c, storage="f32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(c.steps)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        same = sim.bodies()[0]["D"][0] == disp[i]
+        assert same, f"batched and sequential runs differ for {c.name}"
+        sim.close()
+    print(f"[bench] sequential: {t_seq:.2f} s ({lups / t_seq / 1e6:.0f} MLUPS)", file=sys.stderr, flush=True)
+    return {"boxes": len(cases), "cell_updates": lups, "batched_s": round(t_batch, 3),
+            "sequential_s": round(t_seq, 3), "batched_mlups": round(lups / t_batch / 1e6, 1),
+            "sequential_mlups": round(lups / t_seq / 1e6, 1), "speedup": round(t_seq / t_batch, 3),
+            "tuning": best, "bitwise_equal_middle_body_displacement": True}
+
+
+def copy_ceiling(nbytes=2 << 30, reps=20):
+    """Practical HBM ceiling: the best of a few launch shapes of a plain
+    streaming copy of ``nbytes`` (read + write counted), timed with torch
+    events on the stream it runs on."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1108_0786_amd import _abi
+
+    lib = _abi.load()
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    best = 0.0
+    for per_cu in (8, 32, 256):
+        for nt in (0, 1):
+            def run():
+                rc = lib.lbm_copy_kernel(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, per_cu,
+                                         nt, C.c_void_p(stream))
+                assert rc == 0
+            for _ in range(3):
+                run()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                run()
+            b.record()
+            torch.cuda.synchronize()
+            gbs = 2 * nbytes / (a.elapsed_time(b) / reps / 1e3) / 1e9
+            print(f"[bench] copy {per_cu} blocks/CU nontemporal={nt}: {gbs:.0f} GB/s", file=sys.stderr,
+                  flush=True)
+            best = max(best, gbs)
+    del src, dst
+    return best
+
+
 def cpu_baseline(case, steps=3):
     """The oracle as it stands, on a few steps of the same box (single core:
     NumPy elementwise kernels)."""
@@ -101,6 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--legs", default="f32,f64,f16s,bf16s")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-periods", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the swimmer step is built and timed on a single "
@@ -117,6 +207,9 @@ def main():
         results[st] = time_leg(W.plain_at_scale(storage=st), st, args.steps, args.warmup)
     head = results["f32"]
     case = W.plain_at_scale(storage="f32")
+    copy_gbs = copy_ceiling()
+    print(f"[bench] plain copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    batched = None if args.no_batch else batched_leg(args.batch_periods)
     cpu = None if args.no_cpu else cpu_baseline(W.plain_at_scale(storage="f64"))
     line = {
         "metric": "MLUPS & % HBM roofline, fused D3Q19+moving-bead step, FP32 vs FP64/FP16, 1 GPU",
@@ -137,8 +230,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["sweep_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "sweep_kernel<float>", "bytes_per_launch": head["sweep_bytes"],
-                     "launch_us": round(head["sweep_us"], 2)},
+                     "launch_us": round(head["sweep_us"], 2), "copy_ceiling_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(head["sweep_gbs"] / copy_gbs, 4)},
         "cpu_baseline": cpu,
+        "batched_sweep": batched,
         "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in results.items()},
     }

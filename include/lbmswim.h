@@ -25,7 +25,7 @@
  *     at coordinates 0 and n.
  *   - Populations are stored as deviations dF = f - w_alpha from the rest
  *     weights, structure of arrays: element [alpha][k][j][i] at
- *     alpha*N + cell, N = nx*ny*nz.  Storage LBM_F64 and LBM_F32 hold dF;
+ *     alpha*stride + cell, N = nx*ny*nz <= stride.  Storage LBM_F64 and LBM_F32 hold dF;
  *     LBM_F16S and LBM_BF16S hold dF * 2^shift_log2 in IEEE half / bfloat16.
  *     LBM_F64 collides in double, the others in float; forces, torques and the
  *     rigid-body state are always double.
@@ -99,6 +99,10 @@ typedef struct {
     double *traj;             /* device, optional */
     int64_t traj_cap;         /* records in traj */
     void *stream;             /* hipStream_t; all work of the context goes here */
+    int64_t stride;           /* elements from one direction's array to the next,
+                                 >= N (0 means N); each pop buffer holds 19*stride
+                                 elements.  Padding N breaks the power-of-two
+                                 spacing of the 19 streams in HBM. */
 } lbm_params;
 
 /* A rigid body (Sec. 2.2).  Positions are anchor + disp; disp accumulates
@@ -182,6 +186,12 @@ int lbm_get_links(lbm_ctx *ctx, int32_t box, int32_t *cell, int8_t *dir, int8_t 
  * device array dst (19*N, same layout as the populations), zero at body cells. */
 int lbm_export_populations(lbm_ctx *ctx, int32_t box, double *dst);
 
+/* Write the current deviations of n chosen cells of box `box` as double into
+ * dst (device, 19*n, dst[alpha*n + m] for cells[m]); cells is a device array
+ * of n linear cell indices; an index outside the box yields NaN in its
+ * column.  Zero at body cells. */
+int lbm_export_cells(lbm_ctx *ctx, int32_t box, const int32_t *cells, int64_t n, double *dst);
+
 /* Overwrite box `box`'s current populations from the device array src
  * (19*N doubles of dF), converting to the storage type. */
 int lbm_import_populations(lbm_ctx *ctx, int32_t box, const double *src);
@@ -193,7 +203,40 @@ int lbm_step_count(lbm_ctx *ctx, int32_t box, int64_t *steps);
  * force or state became non-finite, LBM_E_CAPACITY if a link list overflowed. */
 int lbm_status(lbm_ctx *ctx);
 
-/* Kernel timing.  With enable = 1, lbm_step records a pair of HIP events
+/* Hand-written reverse mode (adjoint) of nsteps coupled steps of box 0 of a
+ * single-box context, from its current state.  The objective is the linear
+ * function of the final body displacements
+ *     J = sum_b dJ_ddisp[3b..3b+2] . disp_b(t + nsteps),
+ * (dJ_ddisp: host array, nb x 3), e.g. 1/nb on x for the swimmer centroid.
+ * On return *J holds its value and grad[0..2] (host) its derivatives with
+ * respect to the driving amplitude and the phase lag (shared by all drives of
+ * the box, Eqs. FB1-FB3) and the spring stiffness k (shared by all springs,
+ * Eq. spring_i).  The forward states are kept as checkpoints every
+ * checkpoint_every steps and recomputed segment by segment during the reverse
+ * pass (scratch: nsteps/checkpoint_every + checkpoint_every + 1 population
+ * states, two adjoint fields in double, owned by the context).  The mapping
+ * must not change during the run (the flags are held fixed in the reverse
+ * pass): LBM_E_STATE otherwise.  Capsule orientation is treated as a constant
+ * in the reverse pass.  Afterwards the context is in the same state as after
+ * lbm_step(ctx, nsteps).  Synchronising. */
+int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const double *dJ_ddisp,
+                double *J, double *grad);
+
+/* Launch tuning of a context (values outside the listed ones give LBM_E_ARG):
+ *   LBM_TUNE_BLOCK        sweep workgroup size: 128, 256 (default) or 512
+ *   LBM_TUNE_XCD_ORDER    1: give each XCD a contiguous slab of tiles (default 0)
+ *   LBM_TUNE_GRAPH_STEPS  0: launch every kernel; n > 0 (default 32): replay a
+ *                         captured HIP graph of n steps where possible
+ *   LBM_TUNE_FULL_REMAP   1: map the bodies every step even when no cell can
+ *                         have changed side (default 0; results are identical)
+ *   LBM_TUNE_NONTEMPORAL  1: streaming (non-temporal) loads and stores in the
+ *                         sweep's interior path (default 0) */
+enum { LBM_TUNE_BLOCK = 0, LBM_TUNE_XCD_ORDER = 1, LBM_TUNE_GRAPH_STEPS = 2, LBM_TUNE_FULL_REMAP = 3,
+       LBM_TUNE_NONTEMPORAL = 4 };
+int lbm_tune(lbm_ctx *ctx, int32_t key, int64_t value);
+
+/* Kernel timing.  With enable = 1, lbm_step launches every kernel itself (no
+ * graph replay) and records a pair of HIP events
  * on the context's stream around every sweep launch and every coupling
  * launch (and keeps them until lbm_get_timing); enable = 0 stops recording
  * and drops the recorded events.  lbm_get_timing synchronises, and writes the
@@ -201,6 +244,15 @@ int lbm_status(lbm_ctx *ctx);
  * enabled: out_ms[0] sweep, out_ms[1] coupling; out_n likewise. */
 int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 int lbm_get_timing(lbm_ctx *ctx, double out_ms[2], int64_t out_n[2]);
+
+/* Measurement aid, not part of the method: copy `bytes` bytes (a multiple
+ * of 16) from device memory src to device memory dst with a plain streaming
+ * kernel on `stream` (hipStream_t), at most 256 * blocks_per_cu workgroups,
+ * with non-temporal loads and stores if `nontemporal`.  Used as the practical
+ * HBM ceiling and to calibrate hardware byte counters against a known
+ * transfer. */
+int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,
+                    void *stream);
 
 /* Write sizeof(lbm_params), sizeof(lbm_body), sizeof(lbm_spring) and
  * sizeof(lbm_drive) into out[0..3] so that a binding can check its struct

@@ -198,18 +198,24 @@ def momentum_exchange(link_c, link_d, link_b, dft, rho, bodies, dims, periodic, 
     correctly rounded sum, independent of order); the geometric part
     2 w_alpha e_alpha (and its torque) is summed exactly in integers.
     Returns (F, T) as lists of 3-vectors, one per object."""
+    y = nbr[link_d, link_c]
+    return link_forces(link_d, link_b, y, dft[link_d, link_c], rho[link_c], bodies, dims, periodic)
+
+
+def link_forces(link_d, link_b, y, dft_link, rho_link, bodies, dims, periodic):
+    """Eq. hydroF from per-link values: direction alpha, body b, body cell y,
+    the post-collision deviation dF~_alpha(x_f) and the density rho(x_f)."""
     F_out, T_out = [], []
     for b, body in enumerate(bodies):
         sel = link_b == b
-        c = link_c[sel]
         d = link_d[sel]
-        y = nbr[d, c]
-        u = wall_velocity(body, y, dims, periodic)
-        r = lever_arms(body["X"], y, dims, periodic)
+        yy = y[sel]
+        u = wall_velocity(body, yy, dims, periodic)
+        r = lever_arms(body["X"], yy, dims, periodic)
         e = E[d]
         o = OPP[d]
         eu_opp = E[o, 0] * u[0] + E[o, 1] * u[1] + E[o, 2] * u[2]
-        s = 2.0 * dft[d, c] + 6.0 * W[d] * rho[c] * eu_opp
+        s = 2.0 * dft_link[sel] + 6.0 * W[d] * rho_link[sel] * eu_opp
         term = [e[:, 0] * s, e[:, 1] * s, e[:, 2] * s]
         torque = [r[1] * term[2] - r[2] * term[1],
                   r[2] * term[0] - r[0] * term[2],
@@ -218,7 +224,7 @@ def momentum_exchange(link_c, link_d, link_b, dft, rho, bodies, dims, periodic, 
         cw = TWO_W_36[d]
         g_int = [int(np.sum(e[:, k] * cw)) for k in range(3)]
         nx, ny, nz = dims
-        idx = (y % nx, (y // nx) % ny, y // (nx * ny))
+        idx = (yy % nx, (yy // nx) % ny, yy // (nx * ny))
         two_d = []
         fpart = []
         for k in range(3):

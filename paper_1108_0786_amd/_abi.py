@@ -10,13 +10,14 @@ LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_OVERLAP, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_
 ERROR_NAMES = {-1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_OVERLAP", -4: "LBM_E_UNSTABLE",
                -5: "LBM_E_STATE", -6: "LBM_E_CAPACITY"}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+TUNE = {"block": 0, "xcd_order": 1, "graph_steps": 2, "full_remap": 3, "nontemporal": 4}
 TRAJ_DOUBLES = 16
 
 SYMBOLS = [
     "lbm_init", "lbm_init_batch", "lbm_set_bodies", "lbm_set_bodies_box", "lbm_set_step_limit",
     "lbm_step", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
-    "lbm_get_links", "lbm_export_populations", "lbm_import_populations", "lbm_step_count",
-    "lbm_status", "lbm_set_timing", "lbm_get_timing", "lbm_struct_sizes", "lbm_last_error",
+    "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations", "lbm_step_count",
+    "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_copy_kernel", "lbm_struct_sizes", "lbm_last_error",
     "lbm_destroy",
 ]
 
@@ -26,7 +27,8 @@ class LbmParams(C.Structure):
                 ("periodic_mask", C.c_uint32), ("tau", C.c_double),
                 ("storage", C.c_int32), ("shift_log2", C.c_int32),
                 ("pop", C.c_void_p * 2), ("flags", C.c_void_p),
-                ("traj", C.c_void_p), ("traj_cap", C.c_int64), ("stream", C.c_void_p)]
+                ("traj", C.c_void_p), ("traj_cap", C.c_int64), ("stream", C.c_void_p),
+                ("stride", C.c_int64)]
 
 
 class LbmBody(C.Structure):
@@ -82,10 +84,14 @@ def load():
         "lbm_get_links": ([ctx_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)], C.c_int),
         "lbm_export_populations": ([ctx_p, C.c_int32, C.c_void_p], C.c_int),
         "lbm_import_populations": ([ctx_p, C.c_int32, C.c_void_p], C.c_int),
+        "lbm_export_cells": ([ctx_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
         "lbm_step_count": ([ctx_p, C.c_int32, P(C.c_int64)], C.c_int),
         "lbm_status": ([ctx_p], C.c_int),
+        "lbm_adjoint": ([ctx_p, C.c_int64, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)], C.c_int),
+        "lbm_tune": ([ctx_p, C.c_int32, C.c_int64], C.c_int),
         "lbm_set_timing": ([ctx_p, C.c_int32], C.c_int),
         "lbm_get_timing": ([ctx_p, P(C.c_double), P(C.c_int64)], C.c_int),
+        "lbm_copy_kernel": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
         "lbm_struct_sizes": ([P(C.c_int64)], C.c_int),
         "lbm_last_error": ([ctx_p], C.c_char_p),
         "lbm_destroy": ([ctx_p], None),

@@ -37,24 +37,42 @@ constexpr uint8_t kOwnerMask = 0x7f;
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
+// memory access with an optional non-temporal (streaming) hint
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <typename S> struct Storage;
 template <> struct Storage<double> {
     using C = double;
-    static __device__ __forceinline__ double load(const double *p, size_t i, float) { return p[i]; }
-    static __device__ __forceinline__ void store(double *p, size_t i, double v, float) { p[i] = v; }
+    template <bool NT = false>
+    static __device__ __forceinline__ double load(const double *p, size_t i, float) { return ld<NT>(p + i); }
+    template <bool NT = false>
+    static __device__ __forceinline__ void store(double *p, size_t i, double v, float) { st<NT>(p + i, v); }
 };
 template <> struct Storage<float> {
     using C = float;
-    static __device__ __forceinline__ float load(const float *p, size_t i, float) { return p[i]; }
-    static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
+    template <bool NT = false>
+    static __device__ __forceinline__ float load(const float *p, size_t i, float) { return ld<NT>(p + i); }
+    template <bool NT = false>
+    static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { st<NT>(p + i, v); }
 };
 template <> struct Storage<_Float16> {
     using C = float;
+    template <bool NT = false>
     static __device__ __forceinline__ float load(const _Float16 *p, size_t i, float inv_scale) {
-        return (float)p[i] * inv_scale;
+        return (float)ld<NT>(p + i) * inv_scale;
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(_Float16 *p, size_t i, float v, float scale) {
-        p[i] = (_Float16)(v * scale);
+        st<NT>(p + i, (_Float16)(v * scale));
     }
 };
 __device__ __forceinline__ float bf16_to_float(uint16_t b) {
@@ -69,11 +87,13 @@ __device__ __forceinline__ uint16_t float_to_bf16(float f) {
 }
 template <> struct Storage<bf16_t> {
     using C = float;
+    template <bool NT = false>
     static __device__ __forceinline__ float load(const bf16_t *p, size_t i, float inv_scale) {
-        return bf16_to_float(p[i].bits) * inv_scale;
+        return bf16_to_float(ld<NT>(&p[i].bits)) * inv_scale;
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(bf16_t *p, size_t i, float v, float scale) {
-        p[i].bits = float_to_bf16(v * scale);
+        st<NT>(&p[i].bits, float_to_bf16(v * scale));
     }
 };
 
@@ -100,9 +120,27 @@ struct DevDrive {
     long long off_left, off_right;
 };
 
+// Momentum-exchange contribution of one boundary link (Eq. hydroF), written
+// by the sweep: deviation part of e_alpha [2 f~ + 6 w rho e_opp.u_w] and its
+// torque about the body position, plus the integer geometric torque term
+// (2 d + 1) x (36 * 2 w_alpha e_alpha), d the integer lever offset.
+struct LinkRec {
+    double f[3];
+    double t[3];
+    int s[3];
+    int pad;
+};
+
+// One tile of the sweep: `first` is the tile's first cell in box `box`,
+// (i0, j0, k0) its coordinates.
+struct WorkItem {
+    int box, first, i0, j0, k0, pad;
+};
+
 struct BoxDesc {
     int nx, ny, nz, per;       // per: bit 0 x, 1 y, 2 z periodic
     int N, nb, ns, nd;
+    long long stride;          // elements between the arrays of consecutive directions
     double omega;              // 1 / tau
     float omegaf, scale, inv_scale, pad0;
     void *pop0, *pop1;
@@ -110,7 +148,7 @@ struct BoxDesc {
     uint8_t *old_owner;        // N bytes: owner before the last remap
     int *link_cell;
     signed char *link_dir, *link_body;
-    double2 *link_val;         // (dF~_alpha(x_f), rho(x_f)) of each link, written by the sweep
+    LinkRec *link_rec;         // one record per link, written by the sweep
     int *link_base;            // N ints: first link of a boundary cell
     int link_cap;
     int pad1;
@@ -119,11 +157,15 @@ struct BoxDesc {
     DevDrive *drives;
     double *traj;
     long long traj_cap;
+    void *partials;            // momentum-exchange partial sums, one slice per reduction workgroup
+    int *counter;              // reduction workgroups of the current step that have finished
     // mutable state, advanced on the device
     long long step;
     int cur;                   // index of the buffer holding the current populations
     int link_count;
     int status;                // 0 ok, else an lbm error code
+    int map_req;               // 1: the remap kernel must map the bodies
+    int map_lo[3], map_hi[3];  // cell box the remap scans
     int pad2;
 };
 

@@ -1,56 +1,59 @@
-// Per-box coupling kernel, one workgroup per box, run after each sweep:
-//   1. momentum-exchange force and torque of every body (Eq. hydroF), summed
-//      in a fixed order (deterministic), with the geometric part 2 w e of the
-//      link term accumulated exactly in integers;
-//   2. driving forces (Eqs. FB1-FB3), spring-damper forces (Eqs. osci_i/j)
-//      and one semi-implicit Euler step of every body (Alg. 1);
-//   3. the object mapping of the next step (Sec. 2.3): new flags, refill of
-//      uncovered cells, near-body marks and the boundary-link list, skipped
-//      when no cell can have changed side since the last mapping.
+// Per-box coupling kernel, run after each sweep:
+//   1. momentum-exchange force and torque of every body (Eq. hydroF): the
+//      link records written by the sweep are summed by kRedBlocks workgroups
+//      per box into partials, in a fixed order; the geometric part 2 w e of
+//      the link term is accumulated exactly in integers;
+//   2. the last workgroup to finish (a global counter) adds the partials in
+//      block order, adds the driving forces (Eqs. FB1-FB3) and the
+//      spring-damper forces (Eqs. osci_i/j) and advances every body by one
+//      semi-implicit Euler step (Alg. 1);
+//   3. the same workgroup maps the bodies for the next step (Sec. 2.3): new
+//      flags, refill of uncovered cells, near-body marks and the boundary
+//      links, skipped when no cell can have changed side since the last
+//      mapping.
+// All sums are in a fixed order, so results do not depend on which
+// workgroup finishes last.
 #pragma once
 #include "geometry.h"
 
 namespace lbm {
 
 constexpr int kCoupleThreads = 256;
+constexpr int kRedBlocks = 32;  // reduction workgroups per box
 constexpr int kMaxBodies = 16;
+constexpr int kMaxSprings = 64;
+constexpr int kMaxDrives = 16;
 constexpr double kMarginSafety = 1e-9;
 
 enum : int { kModeStep = 0, kModeMapOnly = 1 };
 
+// partial momentum-exchange sums of one body over one slice of the links:
+// F (3), T (3) in double; S (3), G (3) exact integers
+struct Partial {
+    double v[6];
+    long long iv[6];
+};
+
 struct CoupleShared {
+    double wred[kCoupleThreads / 64][3][6];
+    int wredi[kCoupleThreads / 64][3][6];
+    double Fd[kMaxBodies][3], Fs[kMaxBodies][3];
+    int bad[kMaxBodies];
     double red[kCoupleThreads];
-    long long ired[kCoupleThreads];
     int scan[kCoupleThreads];
     double F[kMaxBodies][3], T[kMaxBodies][3];
     int lo[3], hi[3];
-    int do_map;
+    int last;
     int cur;                   // index of the current population buffer
+    // the box's small tables, staged in LDS by the workgroup that finishes the step
+    DevBody body[kMaxBodies];
+    DevSpring spring[kMaxSprings];
+    DevDrive drive[kMaxDrives];
+    double margin[kMaxBodies];
+    double qmap[kMaxBodies][4];
+    double psum[kMaxBodies][6];
+    long long psumi[kMaxBodies][6];
 };
-
-__device__ __forceinline__ double block_sum(double v, CoupleShared &sh) {
-    const int t = threadIdx.x;
-    __syncthreads();
-    sh.red[t] = v;
-    __syncthreads();
-    for (int s = kCoupleThreads / 2; s > 0; s >>= 1) {
-        if (t < s) sh.red[t] = sh.red[t] + sh.red[t + s];
-        __syncthreads();
-    }
-    return sh.red[0];
-}
-
-__device__ __forceinline__ long long block_sum_i(long long v, CoupleShared &sh) {
-    const int t = threadIdx.x;
-    __syncthreads();
-    sh.ired[t] = v;
-    __syncthreads();
-    for (int s = kCoupleThreads / 2; s > 0; s >>= 1) {
-        if (t < s) sh.ired[t] += sh.ired[t + s];
-        __syncthreads();
-    }
-    return sh.ired[0];
-}
 
 __device__ __forceinline__ double block_min(double v, CoupleShared &sh) {
     const int t = threadIdx.x;
@@ -85,121 +88,189 @@ __device__ __forceinline__ double load_dev(const void *p, size_t i, float inv_sc
     return (double)Storage<S>::load((const S *)p, i, inv_scale);
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
-// 1. momentum exchange
+// 1. momentum exchange: workgroup r of a box sums the links
+//    l = r * T + t + k * R * T (T threads, R workgroups), all bodies at once
 // ---------------------------------------------------------------------------
-__device__ void momentum_exchange(BoxDesc &B, CoupleShared &sh) {
+constexpr int kBodyGroup = 3;   // bodies accumulated per pass over the links
+
+__device__ void reduce_links(BoxDesc &B, int r, CoupleShared &sh) {
     const int L = min(B.link_count, B.link_cap);
-    for (int b = 0; b < B.nb; ++b) {
-        const DevBody &bd = B.bodies[b];
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        long long g[3] = {0, 0, 0}, s[3] = {0, 0, 0};
-        for (int l = threadIdx.x; l < L; l += kCoupleThreads) {
-            if (B.link_body[l] != b) continue;
-            const int c = B.link_cell[l];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    Partial *out = (Partial *)B.partials + (size_t)r * kMaxBodies;
+    for (int b0 = 0; b0 < B.nb; b0 += kBodyGroup) {
+        double acc[kBodyGroup][6];
+        int ia[kBodyGroup][6];
+#pragma unroll
+        for (int q = 0; q < kBodyGroup; ++q)
+#pragma unroll
+            for (int v = 0; v < 6; ++v) {
+                acc[q][v] = 0.0;
+                ia[q][v] = 0;
+            }
+        for (int l = r * kCoupleThreads + (int)threadIdx.x; l < L; l += kRedBlocks * kCoupleThreads) {
+            const int bb = B.link_body[l] - b0;
             const int a = B.link_dir[l];
-            int i, j, k, ti, tj, tk;
-            decode_cell(c, B.nx, B.ny, i, j, k);
-            neighbour_rt(a, i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk);
-            double r[3], u[3];
-            int d[3];
-            lever_arm(bd, ti, tj, tk, B.nx, B.ny, B.nz, B.per, r, d);
-            wall_velocity(bd, r, u);
-            const int ea[3] = {ex(a), ey(a), ez(a)};
-            // e_opp . u = -(e_a . u)
-            const double eu = -((double)ea[0] * u[0] + (double)ea[1] * u[1] + (double)ea[2] * u[2]);
-            const double2 v = B.link_val[l];
-            const double sc = 2.0 * v.x + 6.0 * wgt(a) * v.y * eu;
-            const double term[3] = {ea[0] * sc, ea[1] * sc, ea[2] * sc};
-            acc[0] += term[0];
-            acc[1] += term[1];
-            acc[2] += term[2];
-            acc[3] += r[1] * term[2] - r[2] * term[1];
-            acc[4] += r[2] * term[0] - r[0] * term[2];
-            acc[5] += r[0] * term[1] - r[1] * term[0];
+            const LinkRec rec = B.link_rec[l];
             const int cw = two_w36(a);
-            const long long ec[3] = {(long long)ea[0] * cw, (long long)ea[1] * cw, (long long)ea[2] * cw};
-            const long long dd[3] = {2LL * d[0] + 1, 2LL * d[1] + 1, 2LL * d[2] + 1};
-            g[0] += ec[0];
-            g[1] += ec[1];
-            g[2] += ec[2];
-            s[0] += dd[1] * ec[2] - dd[2] * ec[1];
-            s[1] += dd[2] * ec[0] - dd[0] * ec[2];
-            s[2] += dd[0] * ec[1] - dd[1] * ec[0];
+            const int ge[3] = {ex(a) * cw, ey(a) * cw, ez(a) * cw};
+#pragma unroll
+            for (int q = 0; q < kBodyGroup; ++q) {
+                const bool m = bb == q;
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    acc[q][v] += m ? rec.f[v] : 0.0;
+                    acc[q][3 + v] += m ? rec.t[v] : 0.0;
+                    ia[q][v] += m ? rec.s[v] : 0;
+                    ia[q][3 + v] += m ? ge[v] : 0;
+                }
+            }
         }
-        double tot[6];
-        long long gt[3], st[3];
-        for (int q = 0; q < 6; ++q) tot[q] = block_sum(acc[q], sh);
-        for (int q = 0; q < 3; ++q) gt[q] = block_sum_i(g[q], sh);
-        for (int q = 0; q < 3; ++q) st[q] = block_sum_i(s[q], sh);
-        if (threadIdx.x == 0) {
+        // fixed reduction tree: lanes by xor-shuffle, then waves in order
+#pragma unroll
+        for (int q = 0; q < kBodyGroup; ++q)
+#pragma unroll
+            for (int v = 0; v < 6; ++v) {
+                acc[q][v] = wave_sum(acc[q][v]);
+                ia[q][v] = wave_sum_int(ia[q][v]);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < kBodyGroup; ++q)
+#pragma unroll
+                for (int v = 0; v < 6; ++v) {
+                    sh.wred[wave][q][v] = acc[q][v];
+                    sh.wredi[wave][q][v] = ia[q][v];
+                }
+        __syncthreads();
+        if (threadIdx.x < kBodyGroup * 12) {
+            const int q = threadIdx.x / 12, v = threadIdx.x % 12;
+            if (b0 + q < B.nb) {
+                if (v < 6) {
+                    double t = sh.wred[0][q][v];
+                    for (int w = 1; w < kCoupleThreads / 64; ++w) t = t + sh.wred[w][q][v];
+                    out[b0 + q].v[v] = t;
+                } else {
+                    long long t = sh.wredi[0][q][v - 6];
+                    for (int w = 1; w < kCoupleThreads / 64; ++w) t += sh.wredi[w][q][v - 6];
+                    out[b0 + q].iv[v - 6] = t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Force and torque of every body from the partials of all slices, summed in
+// slice order.  Thread (b, v) loads the kRedBlocks partials of value v of
+// body b at once (independent loads), then body b's thread assembles them.
+__device__ void finish_forces(BoxDesc &B, CoupleShared &sh) {
+    const Partial *p = (const Partial *)B.partials;
+    const int t = threadIdx.x;
+    if (t < B.nb * 12) {
+        const int b = t / 12, v = t % 12;
+        if (v < 6) {
+            double x[kRedBlocks];
+#pragma unroll
+            for (int r = 0; r < kRedBlocks; ++r) x[r] = p[(size_t)r * kMaxBodies + b].v[v];
+            double tot = x[0];
+#pragma unroll
+            for (int r = 1; r < kRedBlocks; ++r) tot = tot + x[r];
+            sh.psum[b][v] = tot;
+        } else {
+            long long x[kRedBlocks];
+#pragma unroll
+            for (int r = 0; r < kRedBlocks; ++r) x[r] = p[(size_t)r * kMaxBodies + b].iv[v - 6];
+            long long tot = 0;
+#pragma unroll
+            for (int r = 0; r < kRedBlocks; ++r) tot += x[r];
+            sh.psumi[b][v - 6] = tot;
+        }
+    }
+    __syncthreads();
+    const int b = t;
+    if (b < B.nb) {
 #pragma clang fp contract(off)
-            double G[3], fp[3];
-            for (int q = 0; q < 3; ++q) {
-                G[q] = (double)gt[q] / 36.0;
-                double X = bd.anchor[q] + bd.D[q];
-                fp[q] = X - floor(X);
-            }
-            const double Tg[3] = {(double)st[0] / 72.0 - (fp[1] * G[2] - fp[2] * G[1]),
-                                  (double)st[1] / 72.0 - (fp[2] * G[0] - fp[0] * G[2]),
-                                  (double)st[2] / 72.0 - (fp[0] * G[1] - fp[1] * G[0])};
-            for (int q = 0; q < 3; ++q) {
-                sh.F[b][q] = tot[q] + G[q];
-                sh.T[b][q] = tot[3 + q] + Tg[q];
-            }
+        const DevBody &bd = sh.body[b];
+        double G[3], fp[3];
+        for (int v = 0; v < 3; ++v) {
+            G[v] = (double)sh.psumi[b][3 + v] / 36.0;
+            const double X = bd.anchor[v] + bd.D[v];
+            fp[v] = X - floor(X);
+        }
+        const double Tg[3] = {(double)sh.psumi[b][0] / 72.0 - (fp[1] * G[2] - fp[2] * G[1]),
+                              (double)sh.psumi[b][1] / 72.0 - (fp[2] * G[0] - fp[0] * G[2]),
+                              (double)sh.psumi[b][2] / 72.0 - (fp[0] * G[1] - fp[1] * G[0])};
+        for (int v = 0; v < 3; ++v) {
+            sh.F[b][v] = sh.psum[b][v] + G[v];
+            sh.T[b][v] = sh.psum[b][3 + v] + Tg[v];
         }
     }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// 2. rigid bodies (single thread; a handful of bodies)
+// 2. rigid bodies
 // ---------------------------------------------------------------------------
 __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
     const int nb = B.nb;
     const long long n = B.step;
-    double Fd[kMaxBodies][3], Fs[kMaxBodies][3];
-    for (int b = 0; b < nb; ++b)
-        for (int q = 0; q < 3; ++q) Fd[b][q] = Fs[b][q] = 0.0;
-    // driving, Eqs. FB1-FB3 (delayed right force)
-    for (int e = 0; e < B.nd; ++e) {
-        const DevDrive &dv = B.drives[e];
-        const double om = 2.0 * M_PI / dv.period;
-        double fl = -dv.amplitude * sin(om * (double)n);
-        double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
-        if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
-        if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
-        if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
-        const double fm = -(fl + fr);
-        Fd[dv.left][0] += fl;
-        Fd[dv.right][0] += fr;
-        Fd[dv.middle][0] += fm;
-    }
-    // springs, Eqs. spring_i, damp_i, osci_i/j
-    for (int e = 0; e < B.ns; ++e) {
-        const DevSpring &sp = B.springs[e];
-        const DevBody &bi = B.bodies[sp.i];
-        const DevBody &bj = B.bodies[sp.j];
-        double d[3];
-        for (int q = 0; q < 3; ++q) d[q] = (bi.anchor[q] - bj.anchor[q]) + (bi.D[q] - bj.D[q]);
-        const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const double coef = -sp.k * (ell - sp.rest_len) / ell;
-        for (int q = 0; q < 3; ++q) {
-            const double f = coef * d[q] - sp.gamma * (bi.V[q] - bj.V[q]);
-            Fs[sp.i][q] += f;
-            Fs[sp.j][q] -= f;
+    if (threadIdx.x == 0) {
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < 3; ++q) sh.Fd[b][q] = sh.Fs[b][q] = 0.0;
+        // driving, Eqs. FB1-FB3 (delayed right force)
+        for (int e = 0; e < B.nd; ++e) {
+            const DevDrive &dv = sh.drive[e];
+            const double om = 2.0 * M_PI / dv.period;
+            double fl = -dv.amplitude * sin(om * (double)n);
+            double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
+            if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
+            if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
+            if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
+            const double fm = -(fl + fr);
+            sh.Fd[dv.left][0] += fl;
+            sh.Fd[dv.right][0] += fr;
+            sh.Fd[dv.middle][0] += fm;
+        }
+        // springs, Eqs. spring_i, damp_i, osci_i/j
+        for (int e = 0; e < B.ns; ++e) {
+            const DevSpring &sp = sh.spring[e];
+            const DevBody &bi = sh.body[sp.i];
+            const DevBody &bj = sh.body[sp.j];
+            double d[3];
+            for (int q = 0; q < 3; ++q) d[q] = (bi.anchor[q] - bj.anchor[q]) + (bi.D[q] - bj.D[q]);
+            const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double coef = -sp.k * (ell - sp.rest_len) / ell;
+            for (int q = 0; q < 3; ++q) {
+                const double f = coef * d[q] - sp.gamma * (bi.V[q] - bj.V[q]);
+                sh.Fs[sp.i][q] += f;
+                sh.Fs[sp.j][q] -= f;
+            }
         }
     }
-    bool bad = false;
-    for (int b = 0; b < nb; ++b) {
-        DevBody &bd = B.bodies[b];
+    __syncthreads();
+    // one thread per body: total force (Eq. totalFSwimmer) and time integration
+    const int b = threadIdx.x;
+    if (b < nb) {
+        DevBody &bd = sh.body[b];
         for (int q = 0; q < 3; ++q) {
             bd.F[q] = sh.F[b][q];
             bd.T[q] = sh.T[b][q];
         }
         if (!bd.kinematic) {
             const double m = bd.mass;
-            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((sh.F[b][q] + Fd[b][q]) + Fs[b][q]) / m;
+            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((sh.F[b][q] + sh.Fd[b][q]) + sh.Fs[b][q]) / m;
             // Omega += R diag(1/I) R^T T
             const double w = bd.q[0], x = bd.q[1], y = bd.q[2], z = bd.q[3];
             const double R[3][3] = {
@@ -223,8 +294,10 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
             const double nrm = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
             for (int q = 0; q < 4; ++q) bd.q[q] = qn[q] / nrm;
         }
+        int bad = 0;
         for (int q = 0; q < 3; ++q)
-            if (!isfinite(bd.F[q]) || !isfinite(bd.T[q]) || !isfinite(bd.V[q]) || !isfinite(bd.D[q])) bad = true;
+            if (!isfinite(bd.F[q]) || !isfinite(bd.T[q]) || !isfinite(bd.V[q]) || !isfinite(bd.D[q])) bad = 1;
+        sh.bad[b] = bad;
         if (B.traj && B.traj_cap > 0) {
             double *rec = B.traj + ((size_t)(n % B.traj_cap) * nb + b) * 16;
             for (int q = 0; q < 3; ++q) {
@@ -237,8 +310,18 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
             rec[15] = (double)n;
         }
     }
-    if (bad) B.status = -4;
-    B.step = n + 1;
+    __threadfence_block();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bad = 0;
+        for (int q = 0; q < nb; ++q) bad |= sh.bad[q];
+        if (bad) B.status = -4;
+        B.step = n + 1;
+        sh.cur ^= 1;
+        B.cur = sh.cur;
+    }
+    __threadfence_block();
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -270,32 +353,35 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
     return bound;
 }
 
-template <typename S>
-__device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margins, bool force) {
+// Decide (one thread) whether the mapping must be redone and, if so, the
+// box of cells to scan: the union of every body's old and new bounding box
+// plus two cells.
+__device__ void decide_map(BoxDesc &B, const DevBody *bodies, const double (*qmaps)[4], const double *margins,
+                           bool force) {
     const int nb = B.nb;
-    if (threadIdx.x == 0) {
+    {
         // A body whose position is no longer finite cannot be mapped: report
         // the box as unstable and leave the flags as they are.
         bool finite = true;
         for (int b = 0; b < nb; ++b)
             for (int q = 0; q < 3; ++q) {
-                const DevBody &bd = B.bodies[b];
+                const DevBody &bd = bodies[b];
                 if (!isfinite(bd.anchor[q] + bd.D[q]) || !isfinite(bd.Xmap[q])) finite = false;
             }
         int need = force ? 1 : 0;
         for (int b = 0; b < nb && !need; ++b)
-            if (!(moved_bound(B.bodies[b], qmaps + 4 * b) < margins[b] - kMarginSafety)) need = 1;
+            if (!(moved_bound(bodies[b], qmaps[b]) < margins[b] - kMarginSafety)) need = 1;
         if (!finite) {
             need = 0;
             B.status = -4;
         }
-        sh.do_map = need;
+        B.map_req = need;
         if (need) {
             const int n[3] = {B.nx, B.ny, B.nz};
             for (int q = 0; q < 3; ++q) {
                 double lo = 1e300, hi = -1e300;
                 for (int b = 0; b < nb; ++b) {
-                    const DevBody &bd = B.bodies[b];
+                    const DevBody &bd = bodies[b];
                     const double X = bd.anchor[q] + bd.D[q];
                     const double e = body_extent(bd);
                     lo = fmin(lo, fmin(X, bd.Xmap[q]) - e);
@@ -312,19 +398,30 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
                     l = max(l, 0);
                     h = min(h, n[q] - 1);
                 }
-                sh.lo[q] = l;
-                sh.hi[q] = h;
+                B.map_lo[q] = l;
+                B.map_hi[q] = h;
             }
         }
     }
+}
+
+// The object mapping (Sec. 2.3) over the cell box chosen by decide_map, by
+// one workgroup: new owners, body margins, refill of uncovered cells, then
+// near-body marks and the boundary links in cell order.
+template <typename S>
+__device__ void remap_box(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margins) {
+    const int nb = B.nb;
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q) {
+            sh.lo[q] = B.map_lo[q];
+            sh.hi[q] = B.map_hi[q];
+        }
+    }
     __syncthreads();
-    if (!sh.do_map) return;
     const int bx = sh.hi[0] - sh.lo[0] + 1, by = sh.hi[1] - sh.lo[1] + 1, bz = sh.hi[2] - sh.lo[2] + 1;
     const int ncell = (bx > 0 && by > 0 && bz > 0) ? bx * by * bz : 0;
     const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
-    // pass 1: new owners; remember the old ones; margin of every body
-    double marg[kMaxBodies];
-    for (int b = 0; b < nb; ++b) marg[b] = 1e300;
+    // pass 1: new owners; remember the old ones
     for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
         const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
         const int c = i + nx * (j + ny * k);
@@ -332,19 +429,27 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
         const uint8_t old = B.flags[c] & kOwnerMask;
         int owner = 0;
         for (int b = nb - 1; b >= 0; --b) {
-            const DevBody &bd = B.bodies[b];
             double r[3];
             int d[3];
-            lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
-            const double d2 = core_dist2(bd, r);
-            if (d2 <= bd.radius * bd.radius) owner = b + 1;
-            marg[b] = fmin(marg[b], fabs(sqrt(d2) - bd.radius));
+            lever_arm(B.bodies[b], i, j, k, nx, ny, nz, per, r, d);
+            if (inside(B.bodies[b], r)) owner = b + 1;
         }
         B.old_owner[c] = old;
         B.flags[c] = (uint8_t)owner;
     }
+    // margin of every body: the smallest distance of a scanned cell centre
+    // from its surface; until the body has moved that far no cell changes side
     for (int b = 0; b < nb; ++b) {
-        const double m = block_min(marg[b], sh);
+        double m = 1e300;
+        const DevBody &bd = B.bodies[b];
+        for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
+            const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
+            double r[3];
+            int d[3];
+            lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
+            m = fmin(m, fabs(sqrt(core_dist2(bd, r)) - bd.radius));
+        }
+        m = block_min(m, sh);
         if (threadIdx.x == 0) {
             margins[b] = m;
             for (int q = 0; q < 3; ++q) B.bodies[b].Xmap[q] = B.bodies[b].anchor[q] + B.bodies[b].D[q];
@@ -356,7 +461,7 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
     // pass 2: refill cells that left a body (equilibrium at the body's velocity,
     // density averaged over neighbours that are fluid before and after)
     void *popc = sh.cur ? B.pop1 : B.pop0;
-    const size_t N = (size_t)B.N;
+    const size_t stride = (size_t)B.stride;
     for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
         const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
         const int c = i + nx * (j + ny * k);
@@ -371,7 +476,7 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
             const int nc = ti + nx * (tj + ny * tk);
             if (B.old_owner[nc] != 0 || (B.flags[nc] & kOwnerMask) != 0) continue;
             double s = load_dev<S>(popc, nc, B.inv_scale);
-            for (int q = 1; q < 19; ++q) s = s + load_dev<S>(popc, (size_t)q * N + nc, B.inv_scale);
+            for (int q = 1; q < 19; ++q) s = s + load_dev<S>(popc, (size_t)q * stride + nc, B.inv_scale);
             total = total + s;
             ++count;
         }
@@ -386,7 +491,7 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
         for (int a = 0; a < 19; ++a) {
             const double eu = ex(a) * u[0] + ey(a) * u[1] + ez(a) * u[2];
             const double v = wgt(a) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-            Storage<S>::store((S *)popc, (size_t)a * N + c, (typename Storage<S>::C)v, B.scale);
+            Storage<S>::store((S *)popc, (size_t)a * stride + c, (typename Storage<S>::C)v, B.scale);
         }
     }
     __threadfence_block();
@@ -439,7 +544,31 @@ __device__ void remap(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margi
     if (threadIdx.x == 0) {
         B.link_count = running;
         if (running > B.link_cap) B.status = -6;
+        B.map_req = 0;
     }
+}
+
+
+// Copy n 32-bit words from src to dst with the whole workgroup.
+__device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes) {
+    const int n = bytes / 4;
+    for (int t = threadIdx.x; t < n; t += kCoupleThreads) ((int *)dst)[t] = ((const int *)src)[t];
+}
+
+__device__ void stage_in(const BoxDesc &B, CoupleShared &sh, const double *qmaps, const double *margins) {
+    copy_words(sh.body, B.bodies, (int)sizeof(DevBody) * B.nb);
+    copy_words(sh.spring, B.springs, (int)sizeof(DevSpring) * B.ns);
+    copy_words(sh.drive, B.drives, (int)sizeof(DevDrive) * B.nd);
+    copy_words(sh.margin, margins, (int)sizeof(double) * B.nb);
+    copy_words(sh.qmap, qmaps, (int)sizeof(double) * 4 * B.nb);
+    __syncthreads();
+}
+
+__device__ void stage_out(BoxDesc &B, CoupleShared &sh) {
+    __syncthreads();
+    copy_words(B.bodies, sh.body, (int)sizeof(DevBody) * B.nb);
+    __threadfence_block();
+    __syncthreads();
 }
 
 template <typename S>
@@ -447,23 +576,35 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
                                                                 double *qmaps, double *margins,
                                                                 int mode, int force_map) {
     __shared__ CoupleShared sh;
-    const int bi = active[blockIdx.x];
+    const int bi = active[blockIdx.x / kRedBlocks];
+    const int r = blockIdx.x % kRedBlocks;
     BoxDesc &B = boxes[bi];
     double *qm = qmaps + (size_t)bi * 4 * kMaxBodies;
     double *mg = margins + (size_t)bi * kMaxBodies;
-    if (threadIdx.x == 0) sh.cur = B.cur;
-    __syncthreads();
     if (mode == kModeStep) {
-        momentum_exchange(B, sh);
-        if (threadIdx.x == 0) {
-            rigid_step(B, sh);
-            sh.cur ^= 1;
-            B.cur = sh.cur;
-        }
-        __threadfence_block();
+        reduce_links(B, r, sh);
+        // the last workgroup of this box to finish goes on
+        __threadfence();
         __syncthreads();
+        if (threadIdx.x == 0) sh.last = atomicAdd(B.counter, 1) == kRedBlocks - 1;
+        __syncthreads();
+        if (!sh.last) return;
+        __threadfence();
+        if (threadIdx.x == 0) {
+            *B.counter = 0;
+            sh.cur = B.cur;
+        }
+        stage_in(B, sh, qm, mg);
+        finish_forces(B, sh);
+        rigid_step(B, sh);
+    } else {
+        if (r != 0) return;
+        if (threadIdx.x == 0) sh.cur = B.cur;
+        stage_in(B, sh, qm, mg);
     }
-    remap<S>(B, sh, qm, mg, force_map || mode == kModeMapOnly);
+    if (threadIdx.x == 0) decide_map(B, sh.body, sh.qmap, sh.margin, force_map || mode == kModeMapOnly);
+    stage_out(B, sh);
+    if (B.map_req) remap_box<S>(B, sh, qm, mg);
 }
 
 }  // namespace lbm

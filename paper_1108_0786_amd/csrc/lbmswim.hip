@@ -14,6 +14,7 @@
 
 #include "../../include/lbmswim.h"
 #include "common.h"
+#include "adjoint.h"
 #include "coupling.h"
 #include "sweep.h"
 
@@ -21,11 +22,13 @@ using namespace lbm;
 
 namespace {
 
-constexpr int kSweepBlock = 256;
+constexpr int kDefaultBlock = 256;
+constexpr int kDefaultGraphSteps = 32;
 
 struct HostBox {
     lbm_params p;
     int N = 0;
+    long long stride = 0;
     std::vector<lbm_body> bodies;
     std::vector<lbm_spring> springs;
     std::vector<lbm_drive> drives;
@@ -36,9 +39,11 @@ struct HostBox {
     DevDrive *d_drives = nullptr;
     int *link_cell = nullptr;
     signed char *link_dir = nullptr, *link_body = nullptr;
-    double2 *link_val = nullptr;
+    LinkRec *link_rec = nullptr;
     int *link_base = nullptr;
     uint8_t *old_owner = nullptr;
+    void *partials = nullptr;
+    int *counter = nullptr;
     int link_cap = 0;
     bool mapped = false;
 };
@@ -60,6 +65,27 @@ struct lbm_ctx {
     bool force_map = false;
     bool poisoned = false;
     bool timing = false;
+    int block = kDefaultBlock;
+    int xcd_order = 0;
+    int nontemporal = 0;
+    int graph_steps = kDefaultGraphSteps;
+    int ngrid = 0;                 // sweep grid (tiles padded to a multiple of 8)
+    hipGraphExec_t graph = nullptr;
+    int graph_len = 0;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    // adjoint scratch
+    void *adj_ckpt = nullptr, *adj_seg = nullptr;
+    size_t adj_ckpt_bytes = 0, adj_seg_bytes = 0;
+    double *adj_lam[2] = {nullptr, nullptr};
+    size_t adj_lam_bytes = 0;
+    BodyHist *adj_hist = nullptr;
+    size_t adj_hist_bytes = 0;
+    DevBody *adj_ckpt_bodies = nullptr;
+    size_t adj_ckpt_bodies_bytes = 0;
+    AdjBody *adj_body = nullptr;
+    AdjLinkRec *adj_lrec = nullptr;
+    int adj_lrec_cap = 0;
+    double *adj_grad = nullptr;
     std::vector<hipEvent_t> ev[2];   // start/stop pairs: [0] sweep, [1] coupling
     std::string err;
 };
@@ -92,6 +118,8 @@ int validate_params(lbm_ctx *c, const lbm_params &p) {
     if (!p.pop[0] || !p.pop[1] || !p.flags) return fail(c, LBM_E_ARG, "pop[0], pop[1] and flags are required");
     if (p.pop[0] == p.pop[1]) return fail(c, LBM_E_ARG, "pop[0] and pop[1] must differ");
     if (p.traj && p.traj_cap <= 0) return fail(c, LBM_E_ARG, "traj_cap must be > 0 with traj");
+    if (p.stride != 0 && p.stride < (int64_t)p.nx * p.ny * p.nz)
+        return fail(c, LBM_E_ARG, "stride must be 0 or at least nx*ny*nz");
     if ((p.storage == LBM_F16S || p.storage == LBM_BF16S) && (p.shift_log2 < -30 || p.shift_log2 > 30))
         return fail(c, LBM_E_ARG, "shift_log2 out of range");
     return LBM_OK;
@@ -105,6 +133,7 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.nz = h.p.nz;
     d.per = (int)h.p.periodic_mask;
     d.N = h.N;
+    d.stride = h.stride;
     d.nb = (int)h.bodies.size();
     d.ns = (int)h.springs.size();
     d.nd = (int)h.drives.size();
@@ -120,7 +149,7 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.link_cell = h.link_cell;
     d.link_dir = h.link_dir;
     d.link_body = h.link_body;
-    d.link_val = h.link_val;
+    d.link_rec = h.link_rec;
     d.link_base = h.link_base;
     d.link_cap = h.link_cap;
     d.bodies = h.d_bodies;
@@ -128,6 +157,8 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.drives = h.d_drives;
     d.traj = h.p.traj;
     d.traj_cap = h.p.traj ? h.p.traj_cap : 0;
+    d.partials = h.partials;
+    d.counter = h.counter;
     return d;
 }
 
@@ -163,14 +194,19 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
         HostBox &h = c->boxes[b];
         h.p = params[b];
         h.N = params[b].nx * params[b].ny * params[b].nz;
+        h.stride = params[b].stride ? params[b].stride : h.N;
         if (hipMalloc(&h.link_base, sizeof(int) * h.N) != hipSuccess ||
-            hipMalloc(&h.old_owner, h.N) != hipSuccess) {
+            hipMalloc(&h.old_owner, h.N) != hipSuccess ||
+            hipMalloc(&h.partials, sizeof(Partial) * kRedBlocks * kMaxBodies) != hipSuccess ||
+            hipMalloc(&h.counter, sizeof(int)) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "out of device memory for per-cell scratch");
         }
         if (hipMemsetAsync(h.p.flags, 0, h.N, c->stream) != hipSuccess ||
             hipMemsetAsync(h.old_owner, 0, h.N, c->stream) != hipSuccess ||
-            hipMemsetAsync(h.link_base, 0, sizeof(int) * h.N, c->stream) != hipSuccess) {
+            hipMemsetAsync(h.link_base, 0, sizeof(int) * h.N, c->stream) != hipSuccess ||
+            hipMemsetAsync(h.partials, 0, sizeof(Partial) * kRedBlocks * kMaxBodies, c->stream) != hipSuccess ||
+            hipMemsetAsync(h.counter, 0, sizeof(int), c->stream) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "clearing flags failed");
         }
@@ -195,6 +231,7 @@ double body_extent_h(const lbm_body &b) { return b.radius + (b.shape == LBM_CAPS
 int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb,
                     const lbm_spring *springs, int ns, const lbm_drive *drives, int nd) {
     if (nb < 0 || nb > kMaxBodies) return fail(c, LBM_E_ARG, "between 0 and 16 bodies per box");
+    if (ns > kMaxSprings || nd > kMaxDrives) return fail(c, LBM_E_ARG, "at most 64 springs and 16 drives per box");
     if (ns < 0 || nd < 0 || (nb && !bodies) || (ns && !springs) || (nd && !drives))
         return fail(c, LBM_E_ARG, "null body/spring/drive array");
     const int n[3] = {h.p.nx, h.p.ny, h.p.nz};
@@ -254,16 +291,23 @@ int dispatch_storage(int storage, F &&f) {
     }
 }
 
+// Coupling kernel: kRedBlocks workgroups per active box.
 int launch_couple(lbm_ctx *c, const int *active_dev, int nactive, int mode) {
     if (nactive == 0) return LBM_OK;
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(couple_kernel<S>, dim3(nactive), dim3(kCoupleThreads), 0, c->stream,
+        hipLaunchKernelGGL(couple_kernel<S>, dim3(nactive * kRedBlocks), dim3(kCoupleThreads), 0, c->stream,
                            c->d_boxes, active_dev, c->d_qmaps, c->d_margins, mode, c->force_map ? 1 : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("couple launch: ") + hipGetErrorString(e));
         return LBM_OK;
     });
+}
+
+void drop_graph(lbm_ctx *c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_len = 0;
 }
 
 // Rebuild the sweep tiles and the active-box list for boxes that still run.
@@ -274,13 +318,20 @@ int rebuild_work(lbm_ctx *c) {
         const HostBox &h = c->boxes[b];
         if (h.limit >= 0 && h.steps >= h.limit) continue;
         c->active_host.push_back(b);
-        for (int first = 0; first < h.N; first += kSweepBlock) work.push_back({b, first});
+        const int nx = h.p.nx, ny = h.p.ny;
+        for (int first = 0; first < h.N; first += c->block) {
+            const int i0 = first % nx, rest = first / nx;
+            work.push_back({b, first, i0, rest % ny, rest / ny, 0});
+        }
     }
-    if ((int)work.size() > c->nwork) {
+    const int nwork = (int)work.size();
+    const int ngrid = (nwork + 7) / 8 * 8;
+    if (ngrid > c->ngrid || !c->d_work) {
         if (c->d_work) HIP_TRY(c, hipFree(c->d_work));
-        HIP_TRY(c, hipMalloc(&c->d_work, sizeof(WorkItem) * std::max<size_t>(work.size(), 1)));
+        HIP_TRY(c, hipMalloc(&c->d_work, sizeof(WorkItem) * std::max(ngrid, 8)));
     }
-    c->nwork = (int)work.size();
+    c->nwork = nwork;
+    c->ngrid = ngrid;
     c->nactive = (int)c->active_host.size();
     if (c->nwork)
         HIP_TRY(c, hipMemcpyAsync(c->d_work, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice,
@@ -291,19 +342,72 @@ int rebuild_work(lbm_ctx *c) {
     // the host vectors must outlive the asynchronous copies
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->work_dirty = false;
+    drop_graph(c);
+    return LBM_OK;
+}
+
+template <typename S, int BLOCK>
+int launch_sweep_t(lbm_ctx *c) {
+    if (c->nontemporal)
+        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, true>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream, c->d_boxes,
+                           c->d_work, c->nwork, c->xcd_order);
+    else
+        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, false>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream, c->d_boxes,
+                           c->d_work, c->nwork, c->xcd_order);
     return LBM_OK;
 }
 
 int launch_sweep(lbm_ctx *c) {
     if (c->nwork == 0) return LBM_OK;
-    return dispatch_storage(c->storage, [&](auto *tag) -> int {
+    int rc = dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL((sweep_kernel<S, kSweepBlock>), dim3(c->nwork), dim3(kSweepBlock), 0, c->stream,
-                           c->d_boxes, c->d_work);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
-        return LBM_OK;
+        switch (c->block) {
+            case 128: return launch_sweep_t<S, 128>(c);
+            case 512: return launch_sweep_t<S, 512>(c);
+            default: return launch_sweep_t<S, 256>(c);
+        }
     });
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// One coupled step of every active box: sweep, then coupling.
+int launch_step(lbm_ctx *c) {
+    int rc = launch_sweep(c);
+    if (rc) return rc;
+    return launch_couple(c, c->d_active, c->nactive, kModeStep);
+}
+
+// Capture `len` steps into a graph.  The launches are captured on a private
+// stream (the caller's stream may be the legacy default stream, which cannot
+// be captured); the graph is then launched on the caller's stream.
+int capture_graph(lbm_ctx *c, int len) {
+    drop_graph(c);
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        c->stream = user;
+        return fail(c, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    int rc = LBM_OK;
+    for (int s = 0; s < len && rc == LBM_OK; ++s) rc = launch_step(c);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    c->stream = user;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->graph_len = len;
+    return LBM_OK;
 }
 
 template <typename F>
@@ -385,9 +489,25 @@ __global__ void export_kernel(const BoxDesc *boxes, int bi, double *dst) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t N = (size_t)B.N;
     if (idx >= 19 * N) return;
-    const size_t cell = idx % N;
+    const size_t a = idx / N, cell = idx % N;
     const S *src = (const S *)(B.cur ? B.pop1 : B.pop0);
-    dst[idx] = (B.flags[cell] & kOwnerMask) ? 0.0 : (double)Storage<S>::load(src, idx, B.inv_scale);
+    dst[idx] = (B.flags[cell] & kOwnerMask) ? 0.0
+                                            : (double)Storage<S>::load(src, a * B.stride + cell, B.inv_scale);
+}
+
+template <typename S>
+__global__ void export_cells_kernel(const BoxDesc *boxes, int bi, const int *cells, long long n, double *dst) {
+    const BoxDesc &B = boxes[bi];
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int c = cells[m];
+    const S *src = (const S *)(B.cur ? B.pop1 : B.pop0);
+    const bool ok = c >= 0 && c < B.N;
+    for (int a = 0; a < 19; ++a) {
+        double v = __longlong_as_double(0x7ff8000000000000LL);
+        if (ok) v = (B.flags[c] & kOwnerMask) ? 0.0 : (double)Storage<S>::load(src, (size_t)a * B.stride + c, B.inv_scale);
+        dst[(size_t)a * n + m] = v;
+    }
 }
 
 template <typename S>
@@ -396,13 +516,222 @@ __global__ void import_kernel(const BoxDesc *boxes, int bi, const double *srcd) 
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t N = (size_t)B.N;
     if (idx >= 19 * N) return;
+    const size_t a = idx / N, cell = idx % N;
     S *dst = (S *)(B.cur ? B.pop1 : B.pop0);
-    Storage<S>::store(dst, idx, (typename Storage<S>::C)srcd[idx], B.scale);
+    Storage<S>::store(dst, a * B.stride + cell, (typename Storage<S>::C)srcd[idx], B.scale);
+}
+
+// Plain streaming copy: each thread moves four 16-byte vectors per round with
+// independent loads in flight.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                   size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const u32x4 a = ld<NT>(src + i), b = ld<NT>(src + i + stride), c = ld<NT>(src + i + 2 * stride),
+                    d = ld<NT>(src + i + 3 * stride);
+        st<NT>(dst + i, a);
+        st<NT>(dst + i + stride, b);
+        st<NT>(dst + i + 2 * stride, c);
+        st<NT>(dst + i + 3 * stride, d);
+    }
+    for (; i < n; i += stride) st<NT>(dst + i, ld<NT>(src + i));
+}
+
+__global__ void save_hist_kernel(const BoxDesc *boxes, BodyHist *out) {
+    const BoxDesc &B = boxes[0];
+    const int b = threadIdx.x;
+    if (b >= B.nb) return;
+    const DevBody &d = B.bodies[b];
+    for (int q = 0; q < 3; ++q) {
+        out[b].D[q] = d.D[q];
+        out[b].V[q] = d.V[q];
+        out[b].O[q] = d.O[q];
+    }
+    for (int q = 0; q < 4; ++q) out[b].q[q] = d.q[q];
+}
+
+__global__ void set_state_kernel(BoxDesc *boxes, long long step, int cur) {
+    boxes[0].step = step;
+    boxes[0].cur = cur;
+}
+
+__global__ void init_adjoint_kernel(AdjBody *adj, const double *w, int nb, double *grad) {
+    const int b = threadIdx.x;
+    if (b < 3) grad[b] = 0.0;
+    if (b >= nb) return;
+    AdjBody &a = adj[b];
+    for (int q = 0; q < 3; ++q) {
+        a.lD[q] = w[3 * b + q];
+        a.lV[q] = a.lO[q] = a.lF[q] = a.lT[q] = a.muV[q] = a.lDs[q] = a.lVs[q] = 0.0;
+    }
+}
+
+int grow(lbm_ctx *c, void **p, size_t *have, size_t need) {
+    if (*have >= need && *p) return LBM_OK;
+    if (*p) HIP_TRY(c, hipFree(*p));
+    *p = nullptr;
+    HIP_TRY(c, hipMalloc(p, need));
+    *have = need;
+    return LBM_OK;
+}
+
+template <typename S>
+int adjoint_impl(lbm_ctx *c, int64_t nsteps, int ce, const double *w_host, double *J, double *grad_host) {
+    HostBox &h = c->boxes[0];
+    const int nb = (int)h.bodies.size();
+    const size_t state_bytes = (size_t)19 * h.stride * sizeof(S);
+    const int64_t K = (nsteps + ce - 1) / ce;
+    int rc;
+    // scratch: K checkpoints + the final state; one segment of states
+    if ((rc = grow(c, &c->adj_ckpt, &c->adj_ckpt_bytes, state_bytes * (K + 1)))) return rc;
+    if ((rc = grow(c, &c->adj_seg, &c->adj_seg_bytes, state_bytes * ce))) return rc;
+    for (int q = 0; q < 2; ++q) {
+        size_t have = c->adj_lam_bytes;
+        if ((rc = grow(c, (void **)&c->adj_lam[q], &have, sizeof(double) * 19 * h.stride))) return rc;
+    }
+    c->adj_lam_bytes = sizeof(double) * 19 * h.stride;
+    if ((rc = grow(c, (void **)&c->adj_hist, &c->adj_hist_bytes, sizeof(BodyHist) * nb * (nsteps + 1)))) return rc;
+    if ((rc = grow(c, (void **)&c->adj_ckpt_bodies, &c->adj_ckpt_bodies_bytes, sizeof(DevBody) * kMaxBodies * (K + 1))))
+        return rc;
+    if (!c->adj_body) HIP_TRY(c, hipMalloc(&c->adj_body, sizeof(AdjBody) * kMaxBodies));
+    if (!c->adj_grad) HIP_TRY(c, hipMalloc(&c->adj_grad, sizeof(double) * 4));
+    if (c->adj_lrec_cap < h.link_cap) {
+        if (c->adj_lrec) HIP_TRY(c, hipFree(c->adj_lrec));
+        HIP_TRY(c, hipMalloc(&c->adj_lrec, sizeof(AdjLinkRec) * h.link_cap));
+        c->adj_lrec_cap = h.link_cap;
+    }
+    if (c->work_dirty && (rc = rebuild_work(c))) return rc;
+    // current step, buffer and flags at the start
+    BoxDesc d0;
+    HIP_TRY(c, hipMemcpyAsync(&d0, c->d_boxes, sizeof(BoxDesc), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const long long step0 = d0.step;
+    const int cur0 = d0.cur;
+    std::vector<uint8_t> flags0(h.N), flags1(h.N);
+    HIP_TRY(c, hipMemcpy(flags0.data(), h.p.flags, h.N, hipMemcpyDeviceToHost));
+    auto pop = [&](int cur) { return cur ? h.p.pop[1] : h.p.pop[0]; };
+    auto ckpt = [&](int64_t k) { return (char *)c->adj_ckpt + (size_t)k * state_bytes; };
+    auto seg = [&](int64_t m) { return (char *)c->adj_seg + (size_t)m * state_bytes; };
+    const size_t body_bytes = sizeof(DevBody) * nb;
+    // forward pass with checkpoints and the body history
+    hipLaunchKernelGGL(save_hist_kernel, dim3(1), dim3(64), 0, c->stream, c->d_boxes, c->adj_hist);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int cur = cur0 ^ (int)(s & 1);
+        if (s % ce == 0) {
+            HIP_TRY(c, hipMemcpyAsync(ckpt(s / ce), pop(cur), state_bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->adj_ckpt_bodies + (s / ce) * kMaxBodies, h.d_bodies, body_bytes,
+                                      hipMemcpyDeviceToDevice, c->stream));
+        }
+        if ((rc = launch_step(c))) return rc;
+        hipLaunchKernelGGL(save_hist_kernel, dim3(1), dim3(64), 0, c->stream, c->d_boxes,
+                           c->adj_hist + (size_t)(s + 1) * nb);
+    }
+    const int cur_end = cur0 ^ (int)(nsteps & 1);
+    HIP_TRY(c, hipMemcpyAsync(ckpt(K), pop(cur_end), state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->adj_ckpt_bodies + K * kMaxBodies, h.d_bodies, body_bytes, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpy(flags1.data(), h.p.flags, h.N, hipMemcpyDeviceToHost));
+    for (int i = 0; i < h.N; ++i)
+        if ((flags0[i] & kOwnerMask) != (flags1[i] & kOwnerMask))
+            return fail(c, LBM_E_STATE, "the mapping changed during the run; the adjoint holds the flags fixed");
+    // objective
+    std::vector<BodyHist> fin(nb);
+    HIP_TRY(c, hipMemcpy(fin.data(), c->adj_hist + (size_t)nsteps * nb, sizeof(BodyHist) * nb,
+                         hipMemcpyDeviceToHost));
+    double Jv = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 3; ++q) Jv += w_host[3 * b + q] * fin[b].D[q];
+    *J = Jv;
+    // reverse pass
+    double *wdev = nullptr;
+    HIP_TRY(c, hipMalloc(&wdev, sizeof(double) * 3 * nb));
+    HIP_TRY(c, hipMemcpy(wdev, w_host, sizeof(double) * 3 * nb, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(init_adjoint_kernel, dim3(1), dim3(64), 0, c->stream, c->adj_body, wdev, nb, c->adj_grad);
+    HIP_TRY(c, hipMemsetAsync(c->adj_lam[0], 0, c->adj_lam_bytes, c->stream));
+    int lcur = 0;  // adj_lam[lcur] holds the adjoint of the populations after the step being reversed
+    hipLaunchKernelGGL(adjoint_body_kernel, dim3(1), dim3(kCoupleThreads), 0, c->stream, c->d_boxes, c->adj_body,
+                       (const BodyHist *)nullptr, c->adj_hist + (size_t)(nsteps - 1) * nb, c->adj_lrec,
+                       (long long)(step0 + nsteps - 1), 0, c->adj_grad);
+    const unsigned blocks = (unsigned)((h.N + 255) / 256);
+    for (int64_t k = K - 1; k >= 0; --k) {
+        const int64_t s0 = k * ce, s1 = std::min<int64_t>(s0 + ce, nsteps);
+        const int cur = cur0 ^ (int)(s0 & 1);
+        // restore the checkpoint and recompute the segment's states
+        HIP_TRY(c, hipMemcpyAsync(pop(cur), ckpt(k), state_bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(h.d_bodies, c->adj_ckpt_bodies + k * kMaxBodies, body_bytes,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, c->stream, c->d_boxes, step0 + s0, cur);
+        for (int64_t m = s0; m < s1; ++m) {
+            HIP_TRY(c, hipMemcpyAsync(seg(m - s0), pop(cur0 ^ (int)(m & 1)), state_bytes, hipMemcpyDeviceToDevice,
+                                      c->stream));
+            if (m + 1 < s1 && (rc = launch_step(c))) return rc;
+        }
+        for (int64_t n = s1 - 1; n >= s0; --n) {
+            AdjArgs args;
+            args.state = seg(n - s0);
+            args.lam_next = c->adj_lam[lcur];
+            args.lam = c->adj_lam[lcur ^ 1];
+            args.hist = c->adj_hist + (size_t)n * nb;
+            args.adj = c->adj_body;
+            args.lrec = c->adj_lrec;
+            hipLaunchKernelGGL(adjoint_sweep_kernel<S>, dim3(blocks), dim3(256), 0, c->stream, c->d_boxes, args);
+            const long long nprev = (n >= 1) ? (long long)(step0 + n - 1) : -1;
+            hipLaunchKernelGGL(adjoint_body_kernel, dim3(1), dim3(kCoupleThreads), 0, c->stream, c->d_boxes,
+                               c->adj_body, (const BodyHist *)nullptr,
+                               c->adj_hist + (size_t)(n >= 1 ? n - 1 : 0) * nb, c->adj_lrec, nprev, 1, c->adj_grad);
+            lcur ^= 1;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("adjoint launch: ") + hipGetErrorString(e));
+    HIP_TRY(c, hipMemcpyAsync(grad_host, c->adj_grad, sizeof(double) * 3, hipMemcpyDeviceToHost, c->stream));
+    // back to the state after the forward run
+    HIP_TRY(c, hipMemcpyAsync(pop(cur_end), ckpt(K), state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h.d_bodies, c->adj_ckpt_bodies + K * kMaxBodies, body_bytes, hipMemcpyDeviceToDevice,
+                              c->stream));
+    hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, c->stream, c->d_boxes, step0 + nsteps, cur_end);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(wdev));
+    h.steps += nsteps;
+    return LBM_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const double *dJ_ddisp, double *J,
+                double *grad) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->boxes.size() != 1) return fail(c, LBM_E_ARG, "the adjoint runs on a single-box context");
+    if (nsteps < 1 || checkpoint_every < 1 || !dJ_ddisp || !J || !grad)
+        return fail(c, LBM_E_ARG, "nsteps and checkpoint_every must be >= 1; outputs must be non-null");
+    if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
+    if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
+    return dispatch_storage(c->storage, [&](auto *tag) -> int {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return adjoint_impl<S>(c, nsteps, checkpoint_every, dJ_ddisp, J, grad);
+    });
+}
+
+int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,
+                    void *stream) {
+    if (!src || !dst || bytes <= 0 || (bytes % 16) != 0 || blocks_per_cu < 1) return LBM_E_ARG;
+    const size_t n = (size_t)bytes / 16;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 1023) / 1024, 256 * (size_t)blocks_per_cu);
+    if (nontemporal)
+        hipLaunchKernelGGL(copy_kernel<true>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const u32x4 *)src,
+                           (u32x4 *)dst, n);
+    else
+        hipLaunchKernelGGL(copy_kernel<false>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const u32x4 *)src,
+                           (u32x4 *)dst, n);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
 
 int lbm_init(const lbm_params *params, lbm_ctx **out) { return init_common(params, 1, out); }
 
@@ -438,20 +767,19 @@ int lbm_set_bodies_box(lbm_ctx *c, int32_t box, const lbm_body *bodies, int32_t 
             HIP_TRY(c, hipFree(h.link_cell));
             HIP_TRY(c, hipFree(h.link_dir));
             HIP_TRY(c, hipFree(h.link_body));
-            HIP_TRY(c, hipFree(h.link_val));
+            HIP_TRY(c, hipFree(h.link_rec));
         }
         HIP_TRY(c, hipMalloc(&h.link_cell, sizeof(int) * cap));
         HIP_TRY(c, hipMalloc(&h.link_dir, cap));
         HIP_TRY(c, hipMalloc(&h.link_body, cap));
-        HIP_TRY(c, hipMalloc(&h.link_val, sizeof(double2) * cap));
+        HIP_TRY(c, hipMalloc(&h.link_rec, sizeof(LinkRec) * cap));
         h.link_cap = (int)cap;
     }
     if (!h.d_bodies) {
         HIP_TRY(c, hipMalloc(&h.d_bodies, sizeof(DevBody) * kMaxBodies));
-        HIP_TRY(c, hipMalloc(&h.d_springs, sizeof(DevSpring) * 64));
-        HIP_TRY(c, hipMalloc(&h.d_drives, sizeof(DevDrive) * 16));
+        HIP_TRY(c, hipMalloc(&h.d_springs, sizeof(DevSpring) * kMaxSprings));
+        HIP_TRY(c, hipMalloc(&h.d_drives, sizeof(DevDrive) * kMaxDrives));
     }
-    if (ns > 64 || nd > 16) return fail(c, LBM_E_ARG, "at most 64 springs and 16 drives per box");
     std::vector<DevBody> db(nb);
     for (int b = 0; b < nb; ++b) {
         db[b] = to_dev(bodies[b]);
@@ -509,7 +837,16 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
             const HostBox &h = c->boxes[b];
             if (h.limit >= 0) run = std::min<int64_t>(run, h.limit - h.steps);
         }
-        for (int64_t s = 0; s < run; ++s) {
+        int64_t s = 0;
+        if (!c->timing && c->graph_steps > 0 && run >= c->graph_steps) {
+            if (!c->graph || c->graph_len != c->graph_steps) {
+                rc = capture_graph(c, c->graph_steps);
+                if (rc) return rc;
+            }
+            for (; s + c->graph_len <= run; s += c->graph_len)
+                HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+        }
+        for (; s < run; ++s) {
             rc = timed(c, 0, [&] { return launch_sweep(c); });
             if (rc) return rc;
             rc = timed(c, 1, [&] { return launch_couple(c, c->d_active, c->nactive, kModeStep); });
@@ -603,6 +940,22 @@ int lbm_export_populations(lbm_ctx *c, int32_t box, double *dst) {
     });
 }
 
+int lbm_export_cells(lbm_ctx *c, int32_t box, const int32_t *cells, int64_t n, double *dst) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!cells || !dst))) return fail(c, LBM_E_ARG, "null cells or destination");
+    if (n == 0) return LBM_OK;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    return dispatch_storage(c->storage, [&](auto *tag) -> int {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(export_cells_kernel<S>, dim3(blocks), dim3(256), 0, c->stream, c->d_boxes, (int)box,
+                           (const int *)cells, (long long)n, dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("export launch: ") + hipGetErrorString(e));
+        return LBM_OK;
+    });
+}
+
 int lbm_import_populations(lbm_ctx *c, int32_t box, const double *src) {
     int rc = check_box(c, box);
     if (rc) return rc;
@@ -641,6 +994,39 @@ int lbm_status(lbm_ctx *c) {
         if (d[b].status == LBM_E_CAPACITY)
             return fail(c, LBM_E_CAPACITY, "box " + std::to_string(b) + ": link list overflow");
     }
+    return LBM_OK;
+}
+
+int lbm_tune(lbm_ctx *c, int32_t key, int64_t value) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    switch (key) {
+        case LBM_TUNE_BLOCK:
+            if (value != 128 && value != 256 && value != 512) return fail(c, LBM_E_ARG, "block must be 128, 256 or 512");
+            c->block = (int)value;
+            c->work_dirty = true;
+            break;
+        case LBM_TUNE_XCD_ORDER:
+            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "xcd order is 0 or 1");
+            c->xcd_order = (int)value;
+            break;
+        case LBM_TUNE_GRAPH_STEPS:
+            if (value < 0 || value > 4096) return fail(c, LBM_E_ARG, "graph steps in [0, 4096]");
+            c->graph_steps = (int)value;
+            break;
+        case LBM_TUNE_NONTEMPORAL:
+            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "nontemporal is 0 or 1");
+            c->nontemporal = (int)value;
+            break;
+        case LBM_TUNE_FULL_REMAP:
+            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "full remap is 0 or 1");
+            c->force_map = value != 0;
+            break;
+        default:
+            return fail(c, LBM_E_ARG, "unknown tuning key");
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
     return LBM_OK;
 }
 
@@ -686,6 +1072,17 @@ void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_events(c);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    (void)hipFree(c->adj_ckpt);
+    (void)hipFree(c->adj_seg);
+    (void)hipFree(c->adj_lam[0]);
+    (void)hipFree(c->adj_lam[1]);
+    (void)hipFree(c->adj_hist);
+    (void)hipFree(c->adj_ckpt_bodies);
+    (void)hipFree(c->adj_body);
+    (void)hipFree(c->adj_lrec);
+    (void)hipFree(c->adj_grad);
     for (auto &h : c->boxes) {
         (void)hipFree(h.d_bodies);
         (void)hipFree(h.d_springs);
@@ -693,9 +1090,11 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipFree(h.link_cell);
         (void)hipFree(h.link_dir);
         (void)hipFree(h.link_body);
-        (void)hipFree(h.link_val);
+        (void)hipFree(h.link_rec);
         (void)hipFree(h.link_base);
         (void)hipFree(h.old_owner);
+        (void)hipFree(h.partials);
+        (void)hipFree(h.counter);
     }
     (void)hipFree(c->d_boxes);
     (void)hipFree(c->d_qmaps);

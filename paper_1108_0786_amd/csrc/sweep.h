@@ -3,77 +3,108 @@
 // the post-collision values to the neighbours; populations that would enter
 // a wall are bounced back (Eq. lbm:bounce_back), those that would enter a
 // body are bounced back with the moving-wall term of Sec. 2.3, and for those
-// the link's post-collision value and density are recorded for the
-// momentum-exchange sum (Eq. hydroF).
+// the link's momentum-exchange contribution (Eq. hydroF) is written to the
+// link's record.
 #pragma once
 #include "geometry.h"
 
 namespace lbm {
 
-struct WorkItem {
-    int box;
-    int first;   // first cell of the block's tile
-};
-
-template <typename S>
-struct SweepArgs {
-    BoxDesc *boxes;
-    const WorkItem *work;
-};
+// Moving bounce-back of the link (cell, A) into body `owner`: returns the
+// reflected value and writes the link record.
+template <typename S, int A>
+__device__ __forceinline__ typename Storage<S>::C bounce_moving(const BoxDesc &B, int cell, int owner,
+                                                                int ti, int tj, int tk,
+                                                                typename Storage<S>::C v,
+                                                                typename Storage<S>::C rho, int slot) {
+    using C = typename Storage<S>::C;
+    constexpr int O = opp(A);
+    const DevBody &bd = B.bodies[owner - 1];
+    double r[3], u[3];
+    int d[3];
+    lever_arm(bd, ti, tj, tk, B.nx, B.ny, B.nz, B.per, r, d);
+    wall_velocity(bd, r, u);
+    const double eu = (double)ex(O) * u[0] + (double)ey(O) * u[1] + (double)ez(O) * u[2];
+    const double mw = 6.0 * wgt(A) * (double)rho * eu;
+    const double val = (double)v + mw;
+    if (slot >= 0 && slot < B.link_cap) {
+        const double sc = 2.0 * (double)v + mw;
+        const double t0 = ex(A) * sc, t1 = ey(A) * sc, t2 = ez(A) * sc;
+        LinkRec rec;
+        rec.f[0] = t0;
+        rec.f[1] = t1;
+        rec.f[2] = t2;
+        rec.t[0] = r[1] * t2 - r[2] * t1;
+        rec.t[1] = r[2] * t0 - r[0] * t2;
+        rec.t[2] = r[0] * t1 - r[1] * t0;
+        constexpr int cw = two_w36(A);
+        constexpr int e0 = ex(A) * cw, e1 = ey(A) * cw, e2 = ez(A) * cw;
+        const int d0 = 2 * d[0] + 1, d1 = 2 * d[1] + 1, d2 = 2 * d[2] + 1;
+        rec.s[0] = d1 * e2 - d2 * e1;
+        rec.s[1] = d2 * e0 - d0 * e2;
+        rec.s[2] = d0 * e1 - d1 * e0;
+        rec.pad = 0;
+        B.link_rec[slot] = rec;
+    }
+    return (C)val;
+}
 
 template <typename S, int A>
-__device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, size_t N, int cell, int i,
-                                         int j, int k, uint8_t fl,
-                                         typename Storage<S>::C v,
+__device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, long long stride, int cell, int i,
+                                         int j, int k, bool near, typename Storage<S>::C v,
                                          typename Storage<S>::C rho, int &nlink) {
     using St = Storage<S>;
-    using C = typename St::C;
     int ti, tj, tk;
     if (!neighbour<A>(i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk)) {
-        St::store(dst, (size_t)opp(A) * N + cell, v, B.scale);
+        St::store(dst, (size_t)opp(A) * stride + cell, v, B.scale);
         return;
     }
     const int tcell = ti + B.nx * (tj + B.ny * tk);
-    if (fl & kNearBit) {
+    if (near) {
         const int owner = B.flags[tcell] & kOwnerMask;
         if (owner) {
-            const DevBody &bd = B.bodies[owner - 1];
-            double r[3], u[3];
-            int d[3];
-            lever_arm(bd, ti, tj, tk, B.nx, B.ny, B.nz, B.per, r, d);
-            wall_velocity(bd, r, u);
-            constexpr int O = opp(A);
-            const double eu = (double)ex(O) * u[0] + (double)ey(O) * u[1] + (double)ez(O) * u[2];
-            const double val = (double)v + 6.0 * wgt(A) * (double)rho * eu;
-            St::store(dst, (size_t)O * N + cell, (C)val, B.scale);
             const int slot = B.link_base[cell] + nlink;
             ++nlink;
-            if (slot >= 0 && slot < B.link_cap) B.link_val[slot] = make_double2((double)v, (double)rho);
+            St::store(dst, (size_t)opp(A) * stride + cell,
+                      bounce_moving<S, A>(B, cell, owner, ti, tj, tk, v, rho, slot), B.scale);
             return;
         }
     }
-    St::store(dst, (size_t)A * N + tcell, v, B.scale);
+    St::store(dst, (size_t)A * stride + tcell, v, B.scale);
 }
 
 template <typename S, int A>
 struct PushAll {
-    static __device__ __forceinline__ void run(const BoxDesc &B, S *dst, size_t N, int cell, int i,
-                                               int j, int k, uint8_t fl,
-                                               const typename Storage<S>::C *f,
+    static __device__ __forceinline__ void run(const BoxDesc &B, S *dst, long long stride, int cell, int i,
+                                               int j, int k, bool near, const typename Storage<S>::C *f,
                                                typename Storage<S>::C rho, int &nlink) {
-        push_one<S, A>(B, dst, N, cell, i, j, k, fl, f[A], rho, nlink);
-        PushAll<S, A + 1>::run(B, dst, N, cell, i, j, k, fl, f, rho, nlink);
+        push_one<S, A>(B, dst, stride, cell, i, j, k, near, f[A], rho, nlink);
+        PushAll<S, A + 1>::run(B, dst, stride, cell, i, j, k, near, f, rho, nlink);
     }
 };
 template <typename S>
 struct PushAll<S, 19> {
-    static __device__ __forceinline__ void run(const BoxDesc &, S *, size_t, int, int, int, int,
-                                               uint8_t, const typename Storage<S>::C *,
-                                               typename Storage<S>::C, int &) {}
+    static __device__ __forceinline__ void run(const BoxDesc &, S *, long long, int, int, int, int, bool,
+                                               const typename Storage<S>::C *, typename Storage<S>::C,
+                                               int &) {}
 };
 
 // LBGK collision in deviation form: dF~ = dF + omega (dF_eq - dF),
-// dF_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].
+// dF_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].  Opposite directions
+// share the even part drho + rho (4.5 (e.u)^2 - 1.5 u.u) and differ in the
+// sign of 3 rho e.u.
+template <typename C, int A>
+__device__ __forceinline__ void relax_pair(C *f, C drho, C rho, C ux, C uy, C uz, C usq15, C omega) {
+    constexpr int O = opp(A);
+    const C eu = C(ex(A)) * ux + C(ey(A)) * uy + C(ez(A)) * uz;
+    const C even = drho + rho * (C(4.5) * eu * eu - usq15);
+    const C odd = C(3) * rho * eu;
+    const C fa = C(wgt(A)) * (even + odd);
+    const C fo = C(wgt(A)) * (even - odd);
+    f[A] = f[A] + omega * (fa - f[A]);
+    f[O] = f[O] + omega * (fo - f[O]);
+}
+
 template <typename C>
 __device__ __forceinline__ C collide(C *f, C omega) {
     C drho = f[0];
@@ -86,38 +117,102 @@ __device__ __forceinline__ C collide(C *f, C omega) {
     const C inv = C(1) / rho;
     const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
     const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-    for (int a = 0; a < 19; ++a) {
-        const C eu = C(ex(a)) * ux + C(ey(a)) * uy + C(ez(a)) * uz;
-        const C feq = C(wgt(a)) * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
-        f[a] = f[a] + omega * (feq - f[a]);
-    }
+    f[0] = f[0] + omega * (C(wgt(0)) * (drho - rho * usq15) - f[0]);
+    relax_pair<C, 1>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 3>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 5>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 7>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 9>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 11>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 13>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 15>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 17>(f, drho, rho, ux, uy, uz, usq15, omega);
     return rho;
 }
 
-template <typename S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const WorkItem *work) {
+// Interior push: no wall and no body among the neighbours.  off_p / off_m
+// are the linear offsets of the +1 / -1 neighbour along each axis (with the
+// periodic wrap already applied).
+template <typename S, int A, bool NT>
+struct PushFast {
+    static __device__ __forceinline__ void run(S *dst, long long stride, int cell, const int *off_p,
+                                               const int *off_m, const typename Storage<S>::C *f, float scale) {
+        const int o = (ex(A) > 0 ? off_p[0] : ex(A) < 0 ? off_m[0] : 0) +
+                      (ey(A) > 0 ? off_p[1] : ey(A) < 0 ? off_m[1] : 0) +
+                      (ez(A) > 0 ? off_p[2] : ez(A) < 0 ? off_m[2] : 0);
+        Storage<S>::template store<NT>(dst + (size_t)A * stride, (size_t)(unsigned)(cell + o), f[A], scale);
+        PushFast<S, A + 1, NT>::run(dst, stride, cell, off_p, off_m, f, scale);
+    }
+};
+template <typename S, bool NT>
+struct PushFast<S, 19, NT> {
+    static __device__ __forceinline__ void run(S *, long long, int, const int *, const int *,
+                                               const typename Storage<S>::C *, float) {}
+};
+
+// Map a workgroup to its tile.  With xcd_order, the hardware's round-robin
+// placement of consecutive workgroups on the 8 XCDs is undone so that each
+// XCD sweeps one contiguous slab of tiles (neighbouring rows share its L2).
+__device__ __forceinline__ int tile_index(int xcd_order) {
+    const int w = blockIdx.x;
+    if (!xcd_order) return w;
+    const int per = gridDim.x >> 3;
+    return (w & 7) * per + (w >> 3);
+}
+
+template <typename S, int BLOCK, bool NT>
+__global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
+                                                      int xcd_order) {
     using St = Storage<S>;
     using C = typename St::C;
-    const WorkItem wk = work[blockIdx.x];
+    const int t = tile_index(xcd_order);
+    if (t >= nwork) return;
+    const WorkItem wk = work[t];
     const BoxDesc &B = boxes[wk.box];
     const int cell = wk.first + (int)threadIdx.x;
     if (cell >= B.N) return;
     const uint8_t fl = B.flags[cell];
     if (fl & kOwnerMask) return;  // inside a body: no fluid
-    const size_t N = (size_t)B.N;
+    const long long stride = B.stride;
     const S *src = (const S *)(B.cur ? B.pop1 : B.pop0);
     S *dst = (S *)(B.cur ? B.pop0 : B.pop1);
     C f[19];
 #pragma unroll
-    for (int a = 0; a < 19; ++a) f[a] = St::load(src, (size_t)a * N + cell, B.inv_scale);
+    for (int a = 0; a < 19; ++a) f[a] = St::template load<NT>(src, (size_t)a * stride + cell, B.inv_scale);
+    // coordinates from the tile origin (no integer division)
+    int i = wk.i0 + (int)threadIdx.x, j = wk.j0, k = wk.k0;
+    while (i >= B.nx) {
+        i -= B.nx;
+        if (++j == B.ny) {
+            j = 0;
+            ++k;
+        }
+    }
     const C omega = sizeof(C) == 8 ? (C)B.omega : (C)B.omegaf;
     const C rho = collide<C>(f, omega);
-    int i, j, k;
-    decode_cell(cell, B.nx, B.ny, i, j, k);
+    const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
+    const int sy = nx, sz = nx * ny;
+    const bool at_lo[3] = {i == 0, j == 0, k == 0};
+    const bool at_hi[3] = {i == nx - 1, j == ny - 1, k == nz - 1};
+    const int span[3] = {1, sy, sz};
+    const int len[3] = {nx, ny, nz};
+    int off_p[3], off_m[3];
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool p = (per >> a) & 1;
+        off_p[a] = at_hi[a] ? (1 - len[a]) * span[a] : span[a];
+        off_m[a] = at_lo[a] ? (len[a] - 1) * span[a] : -span[a];
+        wall |= !p && (at_lo[a] || at_hi[a]);
+    }
+    if (!wall && !(fl & kNearBit)) {
+        St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
+        PushFast<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale);
+        return;
+    }
     St::store(dst, (size_t)cell, f[0], B.scale);
     int nlink = 0;
-    PushAll<S, 1>::run(B, dst, N, cell, i, j, k, fl, f, rho, nlink);
+    PushAll<S, 1>::run(B, dst, stride, cell, i, j, k, (fl & kNearBit) != 0, f, rho, nlink);
 }
 
 }  // namespace lbm

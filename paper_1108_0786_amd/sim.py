@@ -51,14 +51,27 @@ def _body_dict(s):
             "V": list(s.vel), "Omega": list(s.omega)}
 
 
+def padded_stride(n, pad=None):
+    """Elements between consecutive directions' arrays: N rounded up to 256
+    elements plus ``pad`` (default 4160 = 65 * 64), so that the 19 streams of a
+    sweep do not sit at a power-of-two spacing in HBM."""
+    if pad is None:
+        pad = DEFAULT_PAD
+    return (n + 255) // 256 * 256 + pad if pad else n
+
+
+DEFAULT_PAD = 4160
+
+
 class _Box:
     """Device buffers of one box (caller-owned memory of the C-ABI)."""
 
-    def __init__(self, case, storage, device, traj_cap, shift_log2):
+    def __init__(self, case, storage, device, traj_cap, shift_log2, pad=None):
         self.case = case
         self.N = case.nx * case.ny * case.nz
+        self.stride = padded_stride(self.N, pad)
         dt = _TORCH_DTYPE[storage]
-        self.pop = [torch.zeros(19 * self.N, dtype=dt, device=device) for _ in range(2)]
+        self.pop = [torch.zeros(19 * self.stride, dtype=dt, device=device) for _ in range(2)]
         self.flags = torch.zeros(self.N, dtype=torch.uint8, device=device)
         nb = max(len(case.bodies), 1)
         self.traj = torch.zeros((traj_cap, nb, _abi.TRAJ_DOUBLES), dtype=torch.float64,
@@ -75,13 +88,15 @@ class _Box:
         p.traj = self.traj.data_ptr() if self.traj is not None else None
         p.traj_cap = traj_cap
         p.stream = torch.cuda.current_stream(device).cuda_stream
+        p.stride = self.stride
         self.params = p
 
 
 class BatchSim:
     """Many independent boxes, each with its own swimmer, in one context."""
 
-    def __init__(self, cases, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None):
+    def __init__(self, cases, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None,
+                 pad=None, tune=None):
         self.lib = _abi.load()
         self.device = torch.device(device)
         storage = storage or cases[0].storage
@@ -89,7 +104,7 @@ class BatchSim:
         if shift_log2 is None:
             shift_log2 = cases[0].shift_log2 if storage in ("f16s", "bf16s") else 0
         with torch.cuda.device(self.device):
-            self.boxes = [_Box(c, storage, self.device, traj_cap, shift_log2) for c in cases]
+            self.boxes = [_Box(c, storage, self.device, traj_cap, shift_log2, pad) for c in cases]
             arr = (LbmParams * len(cases))(*[b.params for b in self.boxes])
             self.ctx = C.c_void_p()
             rc = self.lib.lbm_init_batch(arr, len(cases), C.byref(self.ctx))
@@ -98,6 +113,8 @@ class BatchSim:
                 self.lib.lbm_destroy(self.ctx)
                 self.ctx = None
                 raise err
+            for key, val in (tune or {}).items():
+                self.tune(key, val)
             if df0 is not None:
                 for i, d in enumerate(df0):
                     if d is not None:
@@ -109,6 +126,9 @@ class BatchSim:
     def set_bodies(self, case, box=0):
         bodies, nb, springs, ns, drives, nd = _arrays(case)
         check(self.lib, self.ctx, self.lib.lbm_set_bodies_box(self.ctx, box, bodies, nb, springs, ns, drives, nd))
+
+    def tune(self, key, value):
+        check(self.lib, self.ctx, self.lib.lbm_tune(self.ctx, _abi.TUNE[key], int(value)))
 
     def set_step_limit(self, box, steps):
         check(self.lib, self.ctx, self.lib.lbm_set_step_limit(self.ctx, box, int(steps)))
@@ -156,6 +176,15 @@ class BatchSim:
         c = bx.case
         return out.cpu().numpy().reshape(19, c.nz, c.ny, c.nx)
 
+    def populations_at(self, cells, box=0):
+        """Current deviations at the given linear cell indices, float64 numpy (19, n)."""
+        idx = torch.as_tensor(np.ascontiguousarray(cells, dtype=np.int32)).to(self.device)
+        n = idx.numel()
+        out = torch.empty(19 * max(n, 1), dtype=torch.float64, device=self.device)
+        check(self.lib, self.ctx, self.lib.lbm_export_cells(self.ctx, box, C.c_void_p(idx.data_ptr()), n,
+                                                             C.c_void_p(out.data_ptr())))
+        return out[:19 * n].cpu().numpy().reshape(19, n)
+
     def import_populations(self, df, box=0):
         bx = self.boxes[box]
         t = torch.as_tensor(np.ascontiguousarray(df, dtype=np.float64).reshape(-1)).to(self.device)
@@ -199,10 +228,28 @@ class BatchSim:
 class Sim(BatchSim):
     """One box: ``Sim(case)`` maps ``case.bodies`` and is ready to step."""
 
-    def __init__(self, case, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None):
+    def __init__(self, case, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None,
+                 pad=None, tune=None):
         super().__init__([case], storage=storage, device=device, traj_cap=traj_cap,
-                         shift_log2=shift_log2, df0=None if df0 is None else [df0])
+                         shift_log2=shift_log2, df0=None if df0 is None else [df0], pad=pad, tune=tune)
 
     def centroid_displacement(self):
         b = self.bodies()
         return sum(x["D"][0] for x in b) / len(b)
+
+    def adjoint(self, steps, checkpoint_every=50, weights=None):
+        """Run ``steps`` coupled steps and the hand-written reverse pass.
+
+        J = sum_b weights[b] . disp_b at the end (default: the x displacement
+        of the centroid, 1/nb on x).  Returns (J, dJ/d(amplitude, phase_lag, k))."""
+        nb = len(self.boxes[0].case.bodies)
+        if weights is None:
+            weights = np.zeros((nb, 3))
+            weights[:, 0] = 1.0 / nb
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(nb * 3)
+        J = C.c_double()
+        g = (C.c_double * 3)()
+        check(self.lib, self.ctx, self.lib.lbm_adjoint(
+            self.ctx, int(steps), int(checkpoint_every), w.ctypes.data_as(C.POINTER(C.c_double)),
+            C.byref(J), g))
+        return J.value, np.array(list(g))

@@ -182,3 +182,21 @@ def test_overlapping_bodies_rejected():
     with pytest.raises(LbmError) as e:
         _sim(case, storage="f64")
     assert e.value.code == LBM_E_OVERLAP
+
+
+@pytest.mark.parametrize("tune", [{"graph_steps": 0}, {"graph_steps": 7}, {"block": 128, "xcd_order": 0},
+                                  {"block": 512}, {"full_remap": 1}])
+def test_launch_options_are_bitwise_identical(tune):
+    # graphs, tile sizes, tile order and the remap skip change nothing: the
+    # reductions are in fixed order and the skip only omits no-op remaps
+    case = W.forced_motion(steps=60)
+    print(f"[gpu] launch options {tune}", flush=True)
+    ref = _sim(case, storage="f64", traj_cap=60)
+    ref.step(60)
+    other = _sim(case, storage="f64", traj_cap=60, tune=tune)
+    other.step(60)
+    assert np.array_equal(ref.populations(), other.populations())
+    assert np.array_equal(ref.trajectory(), other.trajectory())
+    assert np.array_equal(ref.flags(), other.flags())
+    ref.close()
+    other.close()

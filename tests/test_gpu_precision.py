@@ -1,0 +1,53 @@
+"""Precision form: the capsule swimmers on the 128x64x64 crop, 1000 steps,
+with FP64, FP32, shifted-FP16 and shifted-BF16 population storage, against
+the FP64 oracle's trajectory (stored by tests/golden/make_goldens.py, which
+calls only the oracle).  The error of each storage type is printed; FP64 and
+FP32 are held to the parity bars, the 16-bit formats to the bound their
+rounding allows."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+# bound on the normalised errors of forces, displacement and centroid velocity
+BOUND = {"f64": 1e-12, "f32": 1e-5, "f16s": 3e-2, "bf16s": 3e-1}
+
+
+@pytest.mark.parametrize("design", ["SCS", "CCC"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_capsule_crop_against_oracle(design, storage):
+    from paper_1108_0786_amd.sim import Sim
+    path = os.path.join(GOLD, f"capsule_crop_{design}.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle trajectory missing (run tests/golden/make_goldens.py)")
+    gold = np.load(path)
+    case = W.capsule_crop(design, storage)
+    steps = int(gold["steps"])
+    print(f"[gpu] precision {case.name} {storage} {steps} steps", flush=True)
+    sim = Sim(case, storage=storage, traj_cap=steps)
+    sim.step(steps)
+    sim.status()
+    tr = sim.trajectory()[:steps]
+    F, D = tr[:, :, 9:12], tr[:, :, 0:3]
+    eF = np.abs(F - gold["F"]).max() / np.abs(gold["F"]).max()
+    eD = np.abs(D[:, :, 0] - gold["D"][:, :, 0]).max() / np.abs(gold["D"][:, :, 0]).max()
+    cg = D[:, :, 0].mean(axis=1)
+    co = gold["D"][:, :, 0].mean(axis=1)
+    eC = np.abs(cg - co).max() / np.abs(co).max()
+    # centroid velocity (per-step displacement of the centroid)
+    vg, vo = np.diff(cg), np.diff(co)
+    eV = np.abs(vg - vo).max() / np.abs(vo).max()
+    df = sim.populations_at(gold["cells"])
+    eP = np.abs(df - gold["df"]).max() / np.abs(gold["df"]).max()
+    print(f"[gpu] precision {design} {storage}: force {eF:.2e} body displacement {eD:.2e} "
+          f"centroid {eC:.2e} centroid velocity {eV:.2e} populations {eP:.2e}", flush=True)
+    assert np.array_equal(sim.flags()[gold["cells"]] & 0x7F, gold["flags"])
+    b = BOUND[storage]
+    assert eF < b and eD < b and eV < b
+    sim.close()

@@ -83,7 +83,7 @@ class Case:
     drives: List[Drive] = field(default_factory=list)
     steps: int = 0
     storage: str = "f64"
-    shift_log2: int = 0
+    shift_log2: int = 16          # scale exponent of the 16-bit storage formats
     note: str = ""
 
     @property
