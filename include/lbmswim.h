@@ -108,11 +108,13 @@ typedef struct {
 /* A rigid body (Sec. 2.2).  Positions are anchor + disp; disp accumulates
  * the motion so that small displacements keep full precision.  quat =
  * (w, x, y, z) rotates the body frame, whose x axis is a capsule's axis.
- * inertia holds the principal moments in the body frame.  kinematic bodies
- * keep their prescribed vel and omega (infinitely heavy). */
+ * inertia holds the principal moments in the body frame.  kinematic = 1:
+ * the body keeps its prescribed vel and omega (infinitely heavy);
+ * kinematic = 2: its rotation is locked (omega prescribed, torque still
+ * computed) while it translates freely; 0: free. */
 typedef struct {
     int32_t shape;            /* LBM_SPHERE or LBM_CAPSULE */
-    int32_t kinematic;
+    int32_t kinematic;        /* 0 free, 1 prescribed motion, 2 rotation locked */
     double radius, half_len;  /* half_len: half the cylinder length of a capsule */
     double mass, inertia[3];
     double anchor[3], disp[3], quat[4], vel[3], omega[3];

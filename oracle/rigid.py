@@ -24,7 +24,12 @@ Readings of points the paper leaves open:
       q  = normalize(q + 1/2 [0, Omega] (x) q),
   where D accumulates the displacement from the fixed anchor and I_w is the
   inertia tensor in world axes (gyroscopic term neglected).  Kinematic bodies
-  keep their prescribed V and Omega.  Bodies never touch, so the contact and
+  keep their prescribed V and Omega; bodies with locked rotation
+  (kinematic = 2) integrate V and D but keep their prescribed Omega (their
+  torque is still computed).  The paper's swimmer bodies only move along the
+  swimmer axis (Sec. 5.1); a capsule of the paper's equal-mass convention is
+  lighter than the fluid it displaces, and for it the explicit rotational
+  update of this integrator is unstable, so the capsule workloads lock it.  Bodies never touch, so the contact and
   constraint stages of Alg. 1 are empty (Sec. 3.1).
 """
 from __future__ import annotations
@@ -82,9 +87,10 @@ def rotation_matrix(q):
 
 def integrate(body, F_tot, T_hydro):
     """One semi-implicit Euler step of a body (Alg. 1, time integration)."""
-    if not body["kinematic"]:
+    if body["kinematic"] != 1:
         m = body["mass"]
         body["V"] = [body["V"][k] + F_tot[k] / m for k in range(3)]
+    if body["kinematic"] == 0:
         R = rotation_matrix(body["quat"])
         inv = np.diag([1.0 / v for v in body["inertia"]])
         Iw_inv = R @ inv @ R.T

@@ -34,7 +34,7 @@ def _body_state(b, dtype):
         "anchor": [float(v) for v in b.anchor],
         "D": [dtype(v) for v in b.disp], "quat": [dtype(v) for v in b.quat],
         "V": [dtype(v) for v in b.vel], "Omega": [dtype(v) for v in b.omega],
-        "kinematic": bool(b.kinematic),
+        "kinematic": int(b.kinematic),
     }
 
 

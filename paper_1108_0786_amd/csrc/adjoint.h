@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kCoupleThreads) void adjoint_body_kernel(const BoxD
             const DevBody &bd = B.bodies[b];
             for (int q = 0; q < 3; ++q) {
                 ab.muV[q] = ab.lV[q] + ab.lD[q];
-                lF[b][q] = bd.kinematic ? 0.0 : ab.muV[q] / bd.mass;
+                lF[b][q] = bd.kinematic == 1 ? 0.0 : ab.muV[q] / bd.mass;
                 ab.lF[q] = lF[b][q];
                 ab.lDs[q] = ab.lVs[q] = 0.0;
             }
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kCoupleThreads) void adjoint_body_kernel(const BoxD
                 {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
             double bt[3];
             for (int p = 0; p < 3; ++p)
-                bt[p] = bd.kinematic ? 0.0
+                bt[p] = bd.kinematic != 0 ? 0.0
                                      : (R[0][p] * ab.lO[0] + R[1][p] * ab.lO[1] + R[2][p] * ab.lO[2]) / bd.inertia[p];
             for (int p = 0; p < 3; ++p) ab.lT[p] = R[p][0] * bt[0] + R[p][1] * bt[1] + R[p][2] * bt[2];
             grad[0] += lF[b][0] * dFa[b];

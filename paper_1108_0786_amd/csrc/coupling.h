@@ -268,9 +268,11 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
             bd.F[q] = sh.F[b][q];
             bd.T[q] = sh.T[b][q];
         }
-        if (!bd.kinematic) {
+        if (bd.kinematic != 1) {
             const double m = bd.mass;
             for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((sh.F[b][q] + sh.Fd[b][q]) + sh.Fs[b][q]) / m;
+        }
+        if (bd.kinematic == 0) {
             // Omega += R diag(1/I) R^T T
             const double w = bd.q[0], x = bd.q[1], y = bd.q[2], z = bd.q[3];
             const double R[3][3] = {

@@ -238,9 +238,10 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
     for (int b = 0; b < nb; ++b) {
         const lbm_body &B = bodies[b];
         if (B.shape != LBM_SPHERE && B.shape != LBM_CAPSULE) return fail(c, LBM_E_ARG, "unknown body shape");
-        if (!(B.radius > 0) || B.half_len < 0 || (!B.kinematic && !(B.mass > 0)))
+        if (B.kinematic < 0 || B.kinematic > 2) return fail(c, LBM_E_ARG, "kinematic must be 0, 1 or 2");
+        if (!(B.radius > 0) || B.half_len < 0 || (B.kinematic != 1 && !(B.mass > 0)))
             return fail(c, LBM_E_ARG, "body radius and mass must be positive");
-        if (!B.kinematic && !(B.inertia[0] > 0 && B.inertia[1] > 0 && B.inertia[2] > 0))
+        if (B.kinematic == 0 && !(B.inertia[0] > 0 && B.inertia[1] > 0 && B.inertia[2] > 0))
             return fail(c, LBM_E_ARG, "body inertia must be positive");
         const double e = body_extent_h(B);
         for (int q = 0; q < 3; ++q) {

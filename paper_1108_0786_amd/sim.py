@@ -20,7 +20,7 @@ _TORCH_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f16s": torch.float1
 def _body_struct(b):
     s = LbmBody()
     s.shape = int(b.shape)
-    s.kinematic = int(bool(b.kinematic))
+    s.kinematic = int(b.kinematic)
     s.radius = float(b.radius)
     s.half_len = float(b.half_len)
     s.mass = float(b.mass)
@@ -46,7 +46,7 @@ def _arrays(case):
 
 
 def _body_dict(s):
-    return {"shape": s.shape, "kinematic": bool(s.kinematic), "radius": s.radius, "half_len": s.half_len,
+    return {"shape": s.shape, "kinematic": int(s.kinematic), "radius": s.radius, "half_len": s.half_len,
             "mass": s.mass, "anchor": list(s.anchor), "D": list(s.disp), "quat": list(s.quat),
             "V": list(s.vel), "Omega": list(s.omega)}
 

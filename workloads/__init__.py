@@ -45,7 +45,7 @@ class Body:
     quat: Tuple[float, float, float, float] = (1.0, 0.0, 0.0, 0.0)  # (w, x, y, z)
     vel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     omega: Tuple[float, float, float] = (0.0, 0.0, 0.0)
-    kinematic: bool = False        # prescribed V and Omega (infinite mass)
+    kinematic: int = 0             # 0 free; 1 prescribed V and Omega; 2 prescribed Omega (rotation locked)
 
 
 @dataclass
@@ -173,7 +173,9 @@ def capsule_swimmer(nx: int, ny: int, nz: int, design: str = "SCS", storage: str
                     steps: int = 5000, shift_log2: int = 16) -> Case:
     """Capsule variant: r=5 bodies, capsules with cylinder length 10 parallel to x,
     surface gap 10 between neighbours; ``design`` is 'SCS' or 'CCC' (middle is
-    the second letter)."""
+    the second letter).  Every body keeps the sphere's mass (Sec. 5.1), so a
+    capsule is lighter than the fluid it displaces; the bodies' rotation is
+    locked (they move along the swimmer axis only, as in Sec. 5.1)."""
     r, h, gap = 5.0, 5.0, 10.0
     kinds = {"S": SPHERE, "C": CAPSULE}
     left, mid, right = (kinds[c] for c in design)
@@ -237,8 +239,44 @@ def forced_motion(steps: int = 400, storage: str = "f64") -> Case:
                 storage=storage)
 
 
+# Sec. 5.1 design study, converted to lattice units: dx = 1 um, the time step
+# fixed by the printed driving frequency (omega = 296057.86703 1/s for a
+# period of 28116 steps), fluid density 1360 kg/m^3 (the printed 1.36 read
+# with the unit of g/cm^3).
+PAPER_SI = {"dx": 1e-6, "omega": 296057.86703, "period": 28116, "rho": 1360.0, "mass": 5.44e-13,
+            "k": 1.72965, "gamma": 1.57237e-7, "amplitude": 1.0e-5}
+
+
+def paper_units():
+    """Lattice values of the Sec. 5.1 parameters: (mass, k, gamma, amplitude)."""
+    si = PAPER_SI
+    dt = (2.0 * math.pi / si["period"]) / si["omega"]
+    mu = si["rho"] * si["dx"] ** 3                  # mass unit
+    return (si["mass"] / mu, si["k"] * dt * dt / mu, si["gamma"] * dt / mu,
+            si["amplitude"] * dt * dt / (mu * si["dx"]))
+
+
+def paper_design(design: str = "a", storage: str = "f64") -> Case:
+    """The three-sphere swimmers of the Sec. 5.1 design study: (a) radius 4,
+    (q) radius 8, surface gaps of 8 cells, equal masses, tau 2/3, centred in a
+    200x100x100 channel (swimmer axis x, periodic; walls in y and z).  The
+    right force starts a quarter period late and the forces are switched off
+    after five periods (left) and a quarter period later (right and middle);
+    196812 steps in all."""
+    r = {"a": 4.0, "q": 8.0}[design]
+    m, k, gamma, a = paper_units()
+    T = PAPER_SI["period"]
+    l0 = 8.0 + 2.0 * r
+    b, s, d = swimmer((100.0, 50.0, 50.0), r=r, l0=(l0, l0), k=k, gamma=gamma, mass=m,
+                      amplitude=a, period=float(T), phase_lag=math.pi / 2, gate_lagged=True,
+                      off_left=5 * T, off_right=5 * T + T // 4)
+    return Case(f"paper_{design}_200x100x100", 200, 100, 100, 2.0 / 3.0, bodies=b, springs=s, drives=[d],
+                steps=196812, storage=storage)
+
+
 def random_small(seed: int, storage: str = "f64") -> Case:
-    """A small random box with one to three free or kinematic spheres/capsules,
+    """A small random box with one to three free, kinematic or rotation-locked
+    spheres/capsules,
     placed without overlap and away from the walls; used for property tests."""
     rng = np.random.default_rng(1000 + seed)
     nx = int(rng.integers(12, 29))
@@ -267,14 +305,17 @@ def random_small(seed: int, storage: str = "f64") -> Case:
                 ok = False
         if not ok:
             continue
-        kin = bool(rng.integers(0, 2))
-        vel = tuple(float(v) for v in rng.uniform(-0.02, 0.02, 3)) if kin else (0.0, 0.0, 0.0)
+        kin = int(rng.integers(0, 3))   # free, prescribed motion, rotation locked
+        vel = tuple(float(v) for v in rng.uniform(-0.02, 0.02, 3)) if kin == 1 else (0.0, 0.0, 0.0)
         omg = tuple(float(v) for v in rng.uniform(-0.01, 0.01, 3)) if kin else (0.0, 0.0, 0.0)
         ang = float(rng.uniform(0, math.pi))
         ax = rng.normal(size=3)
         ax = ax / np.linalg.norm(ax)
         quat = (math.cos(ang / 2),) + tuple(float(v) * math.sin(ang / 2) for v in ax)
-        m = bead_mass(r)
+        # every body at the spheres' density ratio (about 1.49): a free capsule
+        # of the spheres' mass would be lighter than the fluid, and its
+        # rotation unstable under the explicit coupling
+        m = bead_mass(r) * (1.0 + 1.5 * h / r)
         b = make_body(shape, r, m, pos, h, vel=vel, omega=omg, quat=quat, kinematic=kin)
         bodies.append(b)
     springs: List[Spring] = []
