@@ -103,6 +103,15 @@ typedef struct {
                                  >= N (0 means N); each pop buffer holds 19*stride
                                  elements.  Padding N breaks the power-of-two
                                  spacing of the 19 streams in HBM. */
+    int32_t force_average;    /* 0: the rigid-body step of step n uses the
+                                 momentum-exchange force and torque of step n
+                                 (Alg. 2); 1: it uses the mean of those of steps
+                                 n and n-1 (zero before the first step after
+                                 lbm_set_bodies).  The paper does not say; the
+                                 mean removes the period-2 mode that the explicit
+                                 coupling amplifies for tau < 1.  lbm_adjoint
+                                 rejects 1. */
+    int32_t reserved;         /* must be 0 */
 } lbm_params;
 
 /* A rigid body (Sec. 2.2).  Positions are anchor + disp; disp accumulates

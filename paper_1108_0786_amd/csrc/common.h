@@ -151,7 +151,7 @@ struct BoxDesc {
     LinkRec *link_rec;         // one record per link, written by the sweep
     int *link_base;            // N ints: first link of a boundary cell
     int link_cap;
-    int pad1;
+    int force_avg;             // 1: bodies move with the mean of this and the last step's F, T
     DevBody *bodies;
     DevSpring *springs;
     DevDrive *drives;

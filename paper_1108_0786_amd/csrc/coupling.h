@@ -264,13 +264,20 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
     const int b = threadIdx.x;
     if (b < nb) {
         DevBody &bd = sh.body[b];
+        // hydrodynamic force and torque that move the body: this step's sums,
+        // or their mean with the last step's (bd.F, bd.T still hold those)
+        double Fh[3], Th[3];
+        for (int q = 0; q < 3; ++q) {
+            Fh[q] = B.force_avg ? 0.5 * (sh.F[b][q] + bd.F[q]) : sh.F[b][q];
+            Th[q] = B.force_avg ? 0.5 * (sh.T[b][q] + bd.T[q]) : sh.T[b][q];
+        }
         for (int q = 0; q < 3; ++q) {
             bd.F[q] = sh.F[b][q];
             bd.T[q] = sh.T[b][q];
         }
         if (bd.kinematic != 1) {
             const double m = bd.mass;
-            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((sh.F[b][q] + sh.Fd[b][q]) + sh.Fs[b][q]) / m;
+            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((Fh[q] + sh.Fd[b][q]) + sh.Fs[b][q]) / m;
         }
         if (bd.kinematic == 0) {
             // Omega += R diag(1/I) R^T T
@@ -281,7 +288,7 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
                 {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
             double bt[3];
             for (int p = 0; p < 3; ++p)
-                bt[p] = (R[0][p] * sh.T[b][0] + R[1][p] * sh.T[b][1] + R[2][p] * sh.T[b][2]) / bd.inertia[p];
+                bt[p] = (R[0][p] * Th[0] + R[1][p] * Th[1] + R[2][p] * Th[2]) / bd.inertia[p];
             for (int p = 0; p < 3; ++p) bd.O[p] = bd.O[p] + (R[p][0] * bt[0] + R[p][1] * bt[1] + R[p][2] * bt[2]);
         }
         for (int q = 0; q < 3; ++q) bd.D[q] = bd.D[q] + bd.V[q];

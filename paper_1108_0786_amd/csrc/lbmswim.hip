@@ -122,6 +122,8 @@ int validate_params(lbm_ctx *c, const lbm_params &p) {
         return fail(c, LBM_E_ARG, "stride must be 0 or at least nx*ny*nz");
     if ((p.storage == LBM_F16S || p.storage == LBM_BF16S) && (p.shift_log2 < -30 || p.shift_log2 > 30))
         return fail(c, LBM_E_ARG, "shift_log2 out of range");
+    if (p.force_average != 0 && p.force_average != 1) return fail(c, LBM_E_ARG, "force_average must be 0 or 1");
+    if (p.reserved != 0) return fail(c, LBM_E_ARG, "reserved must be 0");
     return LBM_OK;
 }
 
@@ -152,6 +154,7 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.link_rec = h.link_rec;
     d.link_base = h.link_base;
     d.link_cap = h.link_cap;
+    d.force_avg = h.p.force_average;
     d.bodies = h.d_bodies;
     d.springs = h.d_springs;
     d.drives = h.d_drives;
@@ -714,6 +717,8 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
         return fail(c, LBM_E_ARG, "nsteps and checkpoint_every must be >= 1; outputs must be non-null");
     if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
     if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
+    if (c->boxes[0].p.force_average)
+        return fail(c, LBM_E_ARG, "the adjoint covers the plain explicit coupling (force_average = 0)");
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         return adjoint_impl<S>(c, nsteps, checkpoint_every, dJ_ddisp, J, grad);

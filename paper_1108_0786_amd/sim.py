@@ -89,6 +89,7 @@ class _Box:
         p.traj_cap = traj_cap
         p.stream = torch.cuda.current_stream(device).cuda_stream
         p.stride = self.stride
+        p.force_average = int(bool(getattr(case, "force_average", False)))
         self.params = p
 
 

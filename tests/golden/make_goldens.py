@@ -42,8 +42,15 @@ def capsule(design: str) -> None:
     for n in range(case.steps):
         sim.step()
         if n % 50 == 0:
-            print(f"capsule {design}: step {n} ({time.time() - t0:.0f} s)", flush=True)
+            print(f"capsule {design}: step {n} ({time.time() - t0:.0f} s), "
+                  f"max |F| {np.abs(np.array(sim.traj[-1]['F'])).max():.3e}", flush=True)
     sim.map_next()
+    if not (np.all(np.isfinite(sim.df)) and all(np.all(np.isfinite(t["F"])) for t in sim.traj)):
+        raise SystemExit(f"capsule {design}: the oracle run is not finite; nothing written")
+    # the hydrodynamic forces of a stable run stay of the order of the driving
+    Fmax = max(np.abs(np.array(t["F"])).max() for t in sim.traj)
+    if Fmax > 20.0 * case.drives[0].amplitude:
+        raise SystemExit(f"capsule {design}: max |F| {Fmax:.3e} is far above the driving; nothing written")
     F = np.array([t["F"] for t in sim.traj])
     T = np.array([t["T"] for t in sim.traj])
     D = np.array([t["D"] for t in sim.traj])

@@ -49,3 +49,29 @@ def test_rotation_locked_body_translates_and_keeps_omega():
     # the prescribed spin turns the orientation by 1e-3 rad about z
     ang = 2.0 * math.atan2(body["quat"][3], body["quat"][0]) - 2.0 * math.atan2(q0[3], q0[0])
     assert math.isclose(ang, 1e-3, rel_tol=1e-6)
+
+
+def _period2(tau, average, steps=600):
+    b, s, d = W.swimmer((16.0, 12.0, 12.0), r=3.0, l0=(10.0, 10.0), k=0.05, gamma=0.01,
+                        amplitude=5e-4, period=400.0, phase_lag=math.pi / 2)
+    case = W.Case("period2", 32, 24, 24, tau, bodies=b, springs=s, drives=[d], steps=steps,
+                  force_average=average)
+    sim = OracleSim(case)
+    V = []
+    for _ in range(steps):
+        sim.step()
+        V.append([x["V"][0] for x in sim.bodies])
+    V = np.array(V)
+    # the part of the body velocities that alternates from step to step
+    return np.abs(V[1:-1] - 0.5 * (V[:-2] + V[2:])).max(axis=1)
+
+
+def test_two_step_force_mean_removes_the_period2_mode():
+    # tau = 0.6 (over-relaxed collision): with the plain explicit coupling the
+    # alternating part of the velocity grows by orders of magnitude; with the
+    # two-step mean of the hydrodynamic force it decays
+    plain = _period2(0.6, False)
+    mean = _period2(0.6, True)
+    assert plain[-100:].max() > 100.0 * plain[:100].max()
+    assert mean[-100:].max() < mean[:100].max()
+    assert mean[-100:].max() < 1e-3 * plain[-100:].max()
