@@ -30,6 +30,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 
+# HBM bytes per FP32 sweep launch at 256x128x128, from two rocprofv3 counter
+# passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors make the counters
+# read 2 GiB for a 2 GiB copy).  Valid only for the kernel sources whose
+# digest is given; a changed kernel reports null until it is measured again.
+SWEEP_TRAFFIC = {"bytes": 650583010,
+                 "sources": ("common.h", "geometry.h", "sweep.h"),
+                 "sha256": "e011ac28bd955740daf7ffc06f522d5cd1838dd10db4ae804dd8585d9e1d64dc"}
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for name in SWEEP_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1108_0786_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return SWEEP_TRAFFIC["bytes"] if h.hexdigest() == SWEEP_TRAFFIC["sha256"] else None
+
 
 def sweep_bytes(case, n_fluid, storage):
     """Algorithmic HBM bytes of one sweep launch: every fluid cell reads and
@@ -239,13 +256,13 @@ def main():
                                "r 6, rest length 24, FP32 shifted populations",
                    "cells": case.ncells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(head["sweep_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "sweep_kernel<float>", "bytes_per_launch": head["sweep_bytes"],
                      "launch_us": round(head["sweep_us"], 2), "copy_ceiling_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(head["sweep_gbs"] / copy_gbs, 4)},
         "cpu_baseline": cpu,
         "batched_sweep": batched,
-        "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        "legs": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in results.items()},
     }
     print(json.dumps(line))
