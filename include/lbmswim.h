@@ -241,7 +241,8 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *   LBM_TUNE_FULL_REMAP   1: map the bodies every step even when no cell can
  *                         have changed side (default 0; results are identical)
  *   LBM_TUNE_NONTEMPORAL  1: streaming (non-temporal) loads and stores in the
- *                         sweep's interior path (default 0) */
+ *                         sweep's interior path (default 1 for LBM_F16S and
+ *                         LBM_BF16S, 0 otherwise) */
 enum { LBM_TUNE_BLOCK = 0, LBM_TUNE_XCD_ORDER = 1, LBM_TUNE_GRAPH_STEPS = 2, LBM_TUNE_FULL_REMAP = 3,
        LBM_TUNE_NONTEMPORAL = 4 };
 int lbm_tune(lbm_ctx *ctx, int32_t key, int64_t value);
@@ -258,8 +259,9 @@ int lbm_get_timing(lbm_ctx *ctx, double out_ms[2], int64_t out_n[2]);
 
 /* Measurement aid, not part of the method: copy `bytes` bytes (a multiple
  * of 16) from device memory src to device memory dst with a plain streaming
- * kernel on `stream` (hipStream_t), at most 256 * blocks_per_cu workgroups,
- * with non-temporal loads and stores if `nontemporal`.  Used as the practical
+ * kernel on `stream` (hipStream_t): with blocks_per_cu = 0 one 16-byte vector
+ * per thread over the whole range, else at most 256 * blocks_per_cu
+ * workgroups looping over it; non-temporal loads and stores if `nontemporal`.  Used as the practical
  * HBM ceiling and to calibrate hardware byte counters against a known
  * transfer. */
 int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,

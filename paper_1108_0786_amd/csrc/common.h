@@ -37,42 +37,58 @@ constexpr uint8_t kOwnerMask = 0x7f;
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
+// T in the global address space: pointers read from the box descriptor are
+// generic, and casting them lets the compiler use global (not flat) memory
+// instructions
+template <typename T> using global_t = __attribute__((address_space(1))) T;
+
 // memory access with an optional non-temporal (streaming) hint
-template <bool NT, typename T>
-__device__ __forceinline__ T ld(const T *p) {
+template <bool NT, typename P>
+__device__ __forceinline__ auto ld(P p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
-template <bool NT, typename T>
-__device__ __forceinline__ void st(T *p, T v) {
+template <bool NT, typename P, typename T>
+__device__ __forceinline__ void st(P p, T v) {
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
 
+// R is the raw element type in memory; to_c / from_c convert one element.
+// load / store accept generic and global pointers alike.
 template <typename S> struct Storage;
 template <> struct Storage<double> {
     using C = double;
-    template <bool NT = false>
-    static __device__ __forceinline__ double load(const double *p, size_t i, float) { return ld<NT>(p + i); }
-    template <bool NT = false>
-    static __device__ __forceinline__ void store(double *p, size_t i, double v, float) { st<NT>(p + i, v); }
+    using R = double;
+    static __device__ __forceinline__ double to_c(double r, float) { return r; }
+    static __device__ __forceinline__ double from_c(double v, float) { return v; }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ double load(P p, size_t i, float) { return ld<NT>(p + i); }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ void store(P p, size_t i, double v, float) { st<NT>(p + i, v); }
 };
 template <> struct Storage<float> {
     using C = float;
-    template <bool NT = false>
-    static __device__ __forceinline__ float load(const float *p, size_t i, float) { return ld<NT>(p + i); }
-    template <bool NT = false>
-    static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { st<NT>(p + i, v); }
+    using R = float;
+    static __device__ __forceinline__ float to_c(float r, float) { return r; }
+    static __device__ __forceinline__ float from_c(float v, float) { return v; }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ float load(P p, size_t i, float) { return ld<NT>(p + i); }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ void store(P p, size_t i, float v, float) { st<NT>(p + i, v); }
 };
 template <> struct Storage<_Float16> {
     using C = float;
-    template <bool NT = false>
-    static __device__ __forceinline__ float load(const _Float16 *p, size_t i, float inv_scale) {
-        return (float)ld<NT>(p + i) * inv_scale;
+    using R = _Float16;
+    static __device__ __forceinline__ float to_c(_Float16 r, float inv_scale) { return (float)r * inv_scale; }
+    static __device__ __forceinline__ _Float16 from_c(float v, float scale) { return (_Float16)(v * scale); }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ float load(P p, size_t i, float inv_scale) {
+        return to_c(ld<NT>(p + i), inv_scale);
     }
-    template <bool NT = false>
-    static __device__ __forceinline__ void store(_Float16 *p, size_t i, float v, float scale) {
-        st<NT>(p + i, (_Float16)(v * scale));
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ void store(P p, size_t i, float v, float scale) {
+        st<NT>(p + i, from_c(v, scale));
     }
 };
 __device__ __forceinline__ float bf16_to_float(uint16_t b) {
@@ -87,13 +103,16 @@ __device__ __forceinline__ uint16_t float_to_bf16(float f) {
 }
 template <> struct Storage<bf16_t> {
     using C = float;
-    template <bool NT = false>
-    static __device__ __forceinline__ float load(const bf16_t *p, size_t i, float inv_scale) {
-        return bf16_to_float(ld<NT>(&p[i].bits)) * inv_scale;
+    using R = uint16_t;
+    static __device__ __forceinline__ float to_c(uint16_t r, float inv_scale) { return bf16_to_float(r) * inv_scale; }
+    static __device__ __forceinline__ uint16_t from_c(float v, float scale) { return float_to_bf16(v * scale); }
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ float load(P p, size_t i, float inv_scale) {
+        return to_c(ld<NT>(&p[i].bits), inv_scale);
     }
-    template <bool NT = false>
-    static __device__ __forceinline__ void store(bf16_t *p, size_t i, float v, float scale) {
-        st<NT>(&p[i].bits, float_to_bf16(v * scale));
+    template <bool NT = false, typename P>
+    static __device__ __forceinline__ void store(P p, size_t i, float v, float scale) {
+        st<NT>(&p[i].bits, from_c(v, scale));
     }
 };
 

@@ -180,6 +180,9 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     if (!params || nbox < 1 || nbox > 65535) return LBM_E_ARG;
     lbm_ctx *c = new lbm_ctx();
     c->storage = params[0].storage;
+    // streaming hints pay off for the 16-bit formats only (measured on the
+    // 256x128x128 sweep: FP16S/BF16S 4-7% faster, FP32/FP64 5-15% slower)
+    c->nontemporal = (c->storage == LBM_F16S || c->storage == LBM_BF16S) ? 1 : 0;
     c->stream = (hipStream_t)params[0].stream;
     for (int b = 0; b < nbox; ++b) {
         int rc = validate_params(c, params[b]);
@@ -322,6 +325,9 @@ int rebuild_work(lbm_ctx *c) {
         const HostBox &h = c->boxes[b];
         if (h.limit >= 0 && h.steps >= h.limit) continue;
         c->active_host.push_back(b);
+    }
+    for (int b : c->active_host) {
+        const HostBox &h = c->boxes[b];
         const int nx = h.p.nx, ny = h.p.ny;
         for (int first = 0; first < h.N; first += c->block) {
             const int i0 = first % nx, rest = first / nx;
@@ -526,7 +532,8 @@ __global__ void import_kernel(const BoxDesc *boxes, int bi, const double *srcd) 
 }
 
 // Plain streaming copy: each thread moves four 16-byte vectors per round with
-// independent loads in flight.
+// independent loads in flight (a grid that covers the range does one vector
+// per thread).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool NT>
@@ -727,9 +734,13 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
 
 int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,
                     void *stream) {
-    if (!src || !dst || bytes <= 0 || (bytes % 16) != 0 || blocks_per_cu < 1) return LBM_E_ARG;
+    if (!src || !dst || bytes <= 0 || (bytes % 16) != 0 || blocks_per_cu < 0) return LBM_E_ARG;
     const size_t n = (size_t)bytes / 16;
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 1023) / 1024, 256 * (size_t)blocks_per_cu);
+    if ((n + 255) / 256 > 0x7fffffffu) return LBM_E_ARG;
+    // blocks_per_cu = 0: one 16-byte vector per thread over the whole range
+    const unsigned blocks = blocks_per_cu == 0
+                                ? (unsigned)((n + 255) / 256)
+                                : (unsigned)std::min<size_t>((n + 1023) / 1024, 256 * (size_t)blocks_per_cu);
     if (nontemporal)
         hipLaunchKernelGGL(copy_kernel<true>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const u32x4 *)src,
                            (u32x4 *)dst, n);

@@ -92,21 +92,49 @@ struct PushAll<S, 19> {
 // LBGK collision in deviation form: dF~ = dF + omega (dF_eq - dF),
 // dF_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].  Opposite directions
 // share the even part drho + rho (4.5 (e.u)^2 - 1.5 u.u) and differ in the
-// sign of 3 rho e.u.
+// sign of 3 rho e.u.  Every rounding is spelled out (automatic contraction
+// off, fused multiply-adds written as such), so that the collision gives
+// the same bits in every kernel and code path that inlines it.
+template <typename C>
+__device__ __forceinline__ C fmac(C a, C b, C c) {
+    if constexpr (sizeof(C) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+// e_A . u with the zero components left out
+template <typename C, int A>
+__device__ __forceinline__ C edot(C ux, C uy, C uz) {
+#pragma clang fp contract(off)
+    C s = C(0);
+    bool first = true;
+    auto add = [&](int e, C u) {
+        if (e == 0) return;
+        const C t = e > 0 ? u : -u;
+        s = first ? t : s + t;
+        first = false;
+    };
+    add(ex(A), ux);
+    add(ey(A), uy);
+    add(ez(A), uz);
+    return s;
+}
+
 template <typename C, int A>
 __device__ __forceinline__ void relax_pair(C *f, C drho, C rho, C ux, C uy, C uz, C usq15, C omega) {
+#pragma clang fp contract(off)
     constexpr int O = opp(A);
-    const C eu = C(ex(A)) * ux + C(ey(A)) * uy + C(ez(A)) * uz;
-    const C even = drho + rho * (C(4.5) * eu * eu - usq15);
+    const C eu = edot<C, A>(ux, uy, uz);
+    const C even = fmac(rho, fmac(C(4.5) * eu, eu, -usq15), drho);
     const C odd = C(3) * rho * eu;
     const C fa = C(wgt(A)) * (even + odd);
     const C fo = C(wgt(A)) * (even - odd);
-    f[A] = f[A] + omega * (fa - f[A]);
-    f[O] = f[O] + omega * (fo - f[O]);
+    f[A] = fmac(omega, fa - f[A], f[A]);
+    f[O] = fmac(omega, fo - f[O], f[O]);
 }
 
 template <typename C>
 __device__ __forceinline__ C collide(C *f, C omega) {
+#pragma clang fp contract(off)
     C drho = f[0];
 #pragma unroll
     for (int a = 1; a < 19; ++a) drho += f[a];
@@ -116,8 +144,8 @@ __device__ __forceinline__ C collide(C *f, C omega) {
     const C rho = C(1) + drho;
     const C inv = C(1) / rho;
     const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
-    const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
-    f[0] = f[0] + omega * (C(wgt(0)) * (drho - rho * usq15) - f[0]);
+    const C usq15 = C(1.5) * fmac(ux, ux, fmac(uy, uy, uz * uz));
+    f[0] = fmac(omega, C(wgt(0)) * (drho - rho * usq15) - f[0], f[0]);
     relax_pair<C, 1>(f, drho, rho, ux, uy, uz, usq15, omega);
     relax_pair<C, 3>(f, drho, rho, ux, uy, uz, usq15, omega);
     relax_pair<C, 5>(f, drho, rho, ux, uy, uz, usq15, omega);
@@ -135,7 +163,8 @@ __device__ __forceinline__ C collide(C *f, C omega) {
 // periodic wrap already applied).
 template <typename S, int A, bool NT>
 struct PushFast {
-    static __device__ __forceinline__ void run(S *dst, long long stride, int cell, const int *off_p,
+    template <typename P>
+    static __device__ __forceinline__ void run(P dst, long long stride, int cell, const int *off_p,
                                                const int *off_m, const typename Storage<S>::C *f, float scale) {
         const int o = (ex(A) > 0 ? off_p[0] : ex(A) < 0 ? off_m[0] : 0) +
                       (ey(A) > 0 ? off_p[1] : ey(A) < 0 ? off_m[1] : 0) +
@@ -146,7 +175,8 @@ struct PushFast {
 };
 template <typename S, bool NT>
 struct PushFast<S, 19, NT> {
-    static __device__ __forceinline__ void run(S *, long long, int, const int *, const int *,
+    template <typename P>
+    static __device__ __forceinline__ void run(P, long long, int, const int *, const int *,
                                                const typename Storage<S>::C *, float) {}
 };
 
@@ -174,8 +204,10 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
     const uint8_t fl = B.flags[cell];
     if (fl & kOwnerMask) return;  // inside a body: no fluid
     const long long stride = B.stride;
-    const S *src = (const S *)(B.cur ? B.pop1 : B.pop0);
-    S *dst = (S *)(B.cur ? B.pop0 : B.pop1);
+    // the population buffers live in global memory: say so, so that the
+    // loads and stores of the interior path are global, not flat
+    const global_t<S> *src = (const global_t<S> *)(B.cur ? B.pop1 : B.pop0);
+    global_t<S> *dst = (global_t<S> *)(B.cur ? B.pop0 : B.pop1);
     C f[19];
 #pragma unroll
     for (int a = 0; a < 19; ++a) f[a] = St::template load<NT>(src, (size_t)a * stride + cell, B.inv_scale);
@@ -210,9 +242,10 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
         PushFast<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale);
         return;
     }
-    St::store(dst, (size_t)cell, f[0], B.scale);
+    S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
+    St::store(gdst, (size_t)cell, f[0], B.scale);
     int nlink = 0;
-    PushAll<S, 1>::run(B, dst, stride, cell, i, j, k, (fl & kNearBit) != 0, f, rho, nlink);
+    PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, (fl & kNearBit) != 0, f, rho, nlink);
 }
 
 }  // namespace lbm

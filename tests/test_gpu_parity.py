@@ -185,7 +185,7 @@ def test_overlapping_bodies_rejected():
 
 
 @pytest.mark.parametrize("tune", [{"graph_steps": 0}, {"graph_steps": 7}, {"block": 128, "xcd_order": 0},
-                                  {"block": 512}, {"full_remap": 1}])
+                                  {"block": 512}, {"full_remap": 1}, {"nontemporal": 1}])
 def test_launch_options_are_bitwise_identical(tune):
     # graphs, tile sizes, tile order and the remap skip change nothing: the
     # reductions are in fixed order and the skip only omits no-op remaps

@@ -39,15 +39,21 @@ def test_capsule_crop_against_oracle(design, storage):
     eD = np.abs(D[:, :, 0] - gold["D"][:, :, 0]).max() / np.abs(gold["D"][:, :, 0]).max()
     cg = D[:, :, 0].mean(axis=1)
     co = gold["D"][:, :, 0].mean(axis=1)
-    eC = np.abs(cg - co).max() / np.abs(co).max()
+    # the centroid is the mean of bodies moving in antiphase, much smaller than
+    # their displacements: its error is measured on the bodies' scale
+    dscale = np.abs(gold["D"][:, :, 0]).max()
+    eC = np.abs(cg - co).max() / dscale
     # centroid velocity (per-step displacement of the centroid)
     vg, vo = np.diff(cg), np.diff(co)
     eV = np.abs(vg - vo).max() / np.abs(vo).max()
     df = sim.populations_at(gold["cells"])
     eP = np.abs(df - gold["df"]).max() / np.abs(gold["df"]).max()
     print(f"[gpu] precision {design} {storage}: force {eF:.2e} body displacement {eD:.2e} "
-          f"centroid {eC:.2e} centroid velocity {eV:.2e} populations {eP:.2e}", flush=True)
+          f"centroid (on the bodies' scale) {eC:.2e} centroid velocity {eV:.2e} populations {eP:.2e}", flush=True)
     assert np.array_equal(sim.flags()[gold["cells"]] & 0x7F, gold["flags"])
     b = BOUND[storage]
-    assert eF < b and eD < b and eV < b
+    assert eF < b and eD < b and eC < b
+    # the velocity is the difference of consecutive centroid positions, so its
+    # error bound is twice the displacement bound on the scale max|D| / max|v|
+    assert eV < 2.0 * b * max(1.0, dscale / np.abs(vo).max())
     sim.close()
