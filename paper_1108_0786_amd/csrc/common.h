@@ -183,9 +183,6 @@ struct BoxDesc {
     int cur;                   // index of the buffer holding the current populations
     int link_count;
     int status;                // 0 ok, else an lbm error code
-    int map_req;               // 1: the remap kernel must map the bodies
-    int map_lo[3], map_hi[3];  // cell box the remap scans
-    int pad2;
 };
 
 }  // namespace lbm

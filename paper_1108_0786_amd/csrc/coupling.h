@@ -37,12 +37,14 @@ struct Partial {
 struct CoupleShared {
     double wred[kCoupleThreads / 64][3][6];
     int wredi[kCoupleThreads / 64][3][6];
-    double Fd[kMaxBodies][3], Fs[kMaxBodies][3];
+    double drv[kMaxDrives][3];  // driving forces of each drive: left, right, middle (x components)
+    double spr[kMaxSprings][3]; // force of each spring on its body i (body j feels the opposite)
     int bad[kMaxBodies];
     double red[kCoupleThreads];
     int scan[kCoupleThreads];
     double F[kMaxBodies][3], T[kMaxBodies][3];
-    int lo[3], hi[3];
+    int lo[3], hi[3];          // cell box the remap scans (when map_req)
+    int map_req;               // 1: this step ends with a remap
     int last;
     int cur;                   // index of the current population buffer
     // the box's small tables, staged in LDS by the workgroup that finishes the step
@@ -105,7 +107,7 @@ __device__ __forceinline__ int wave_sum_int(int v) {
 // ---------------------------------------------------------------------------
 constexpr int kBodyGroup = 3;   // bodies accumulated per pass over the links
 
-__device__ void reduce_links(BoxDesc &B, int r, CoupleShared &sh) {
+__device__ void reduce_links(const BoxDesc &B, int r, CoupleShared &sh) {
     const int L = min(B.link_count, B.link_cap);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     Partial *out = (Partial *)B.partials + (size_t)r * kMaxBodies;
@@ -175,7 +177,7 @@ __device__ void reduce_links(BoxDesc &B, int r, CoupleShared &sh) {
 // Force and torque of every body from the partials of all slices, summed in
 // slice order.  Thread (b, v) loads the kRedBlocks partials of value v of
 // body b at once (independent loads), then body b's thread assembles them.
-__device__ void finish_forces(BoxDesc &B, CoupleShared &sh) {
+__device__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
     const Partial *p = (const Partial *)B.partials;
     const int t = threadIdx.x;
     if (t < B.nb * 12) {
@@ -223,47 +225,59 @@ __device__ void finish_forces(BoxDesc &B, CoupleShared &sh) {
 // ---------------------------------------------------------------------------
 // 2. rigid bodies
 // ---------------------------------------------------------------------------
-__device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
+// B is the kernel's snapshot of the box descriptor (read only); the step
+// counter, buffer index and status go to the descriptor itself, Bg.
+__device__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
     const int nb = B.nb;
     const long long n = B.step;
-    if (threadIdx.x == 0) {
-        for (int b = 0; b < nb; ++b)
-            for (int q = 0; q < 3; ++q) sh.Fd[b][q] = sh.Fs[b][q] = 0.0;
-        // driving, Eqs. FB1-FB3 (delayed right force)
-        for (int e = 0; e < B.nd; ++e) {
-            const DevDrive &dv = sh.drive[e];
-            const double om = 2.0 * M_PI / dv.period;
-            double fl = -dv.amplitude * sin(om * (double)n);
-            double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
-            if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
-            if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
-            if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
-            const double fm = -(fl + fr);
-            sh.Fd[dv.left][0] += fl;
-            sh.Fd[dv.right][0] += fr;
-            sh.Fd[dv.middle][0] += fm;
-        }
-        // springs, Eqs. spring_i, damp_i, osci_i/j
-        for (int e = 0; e < B.ns; ++e) {
-            const DevSpring &sp = sh.spring[e];
-            const DevBody &bi = sh.body[sp.i];
-            const DevBody &bj = sh.body[sp.j];
-            double d[3];
-            for (int q = 0; q < 3; ++q) d[q] = (bi.anchor[q] - bj.anchor[q]) + (bi.D[q] - bj.D[q]);
-            const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            const double coef = -sp.k * (ell - sp.rest_len) / ell;
-            for (int q = 0; q < 3; ++q) {
-                const double f = coef * d[q] - sp.gamma * (bi.V[q] - bj.V[q]);
-                sh.Fs[sp.i][q] += f;
-                sh.Fs[sp.j][q] -= f;
-            }
-        }
+    const int t = threadIdx.x;
+    // driving, Eqs. FB1-FB3 (delayed right force): one thread per drive
+    if (t < B.nd) {
+        const DevDrive &dv = sh.drive[t];
+        const double om = 2.0 * M_PI / dv.period;
+        double fl = -dv.amplitude * sin(om * (double)n);
+        double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
+        if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
+        if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
+        if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
+        sh.drv[t][0] = fl;
+        sh.drv[t][1] = fr;
+        sh.drv[t][2] = -(fl + fr);
+    }
+    // springs, Eqs. spring_i, damp_i, osci_i/j: one thread per spring, in the
+    // second wave
+    const int e = t - 64;
+    if (e >= 0 && e < B.ns) {
+        const DevSpring &sp = sh.spring[e];
+        const DevBody &bi = sh.body[sp.i];
+        const DevBody &bj = sh.body[sp.j];
+        double d[3];
+        for (int q = 0; q < 3; ++q) d[q] = (bi.anchor[q] - bj.anchor[q]) + (bi.D[q] - bj.D[q]);
+        const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double coef = -sp.k * (ell - sp.rest_len) / ell;
+        for (int q = 0; q < 3; ++q) sh.spr[e][q] = coef * d[q] - sp.gamma * (bi.V[q] - bj.V[q]);
     }
     __syncthreads();
     // one thread per body: total force (Eq. totalFSwimmer) and time integration
-    const int b = threadIdx.x;
+    const int b = t;
     if (b < nb) {
         DevBody &bd = sh.body[b];
+        // this body's driving and spring forces, summed drive by drive and
+        // spring by spring (the order of the plain definition)
+        double Fd[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < B.nd; ++k) {
+            const DevDrive &dv = sh.drive[k];
+            if (dv.left == b) Fd[0] = Fd[0] + sh.drv[k][0];
+            if (dv.right == b) Fd[0] = Fd[0] + sh.drv[k][1];
+            if (dv.middle == b) Fd[0] = Fd[0] + sh.drv[k][2];
+        }
+        for (int k = 0; k < B.ns; ++k) {
+            const DevSpring &sp = sh.spring[k];
+            if (sp.i == b)
+                for (int q = 0; q < 3; ++q) Fs[q] = Fs[q] + sh.spr[k][q];
+            if (sp.j == b)
+                for (int q = 0; q < 3; ++q) Fs[q] = Fs[q] - sh.spr[k][q];
+        }
         // hydrodynamic force and torque that move the body: this step's sums,
         // or their mean with the last step's (bd.F, bd.T still hold those)
         double Fh[3], Th[3];
@@ -277,7 +291,7 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
         }
         if (bd.kinematic != 1) {
             const double m = bd.mass;
-            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((Fh[q] + sh.Fd[b][q]) + sh.Fs[b][q]) / m;
+            for (int q = 0; q < 3; ++q) bd.V[q] = bd.V[q] + ((Fh[q] + Fd[q]) + Fs[q]) / m;
         }
         if (bd.kinematic == 0) {
             // Omega += R diag(1/I) R^T T
@@ -319,17 +333,15 @@ __device__ void rigid_step(BoxDesc &B, CoupleShared &sh) {
             rec[15] = (double)n;
         }
     }
-    __threadfence_block();
     __syncthreads();
     if (threadIdx.x == 0) {
         int bad = 0;
         for (int q = 0; q < nb; ++q) bad |= sh.bad[q];
-        if (bad) B.status = -4;
-        B.step = n + 1;
+        if (bad) Bg.status = -4;
+        Bg.step = n + 1;
         sh.cur ^= 1;
-        B.cur = sh.cur;
+        Bg.cur = sh.cur;
     }
-    __threadfence_block();
     __syncthreads();
 }
 
@@ -362,55 +374,61 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
     return bound;
 }
 
-// Decide (one thread) whether the mapping must be redone and, if so, the
-// box of cells to scan: the union of every body's old and new bounding box
-// plus two cells.
-__device__ void decide_map(BoxDesc &B, const DevBody *bodies, const double (*qmaps)[4], const double *margins,
-                           bool force) {
-    const int nb = B.nb;
-    {
-        // A body whose position is no longer finite cannot be mapped: report
-        // the box as unstable and leave the flags as they are.
-        bool finite = true;
-        for (int b = 0; b < nb; ++b)
-            for (int q = 0; q < 3; ++q) {
-                const DevBody &bd = bodies[b];
-                if (!isfinite(bd.anchor[q] + bd.D[q]) || !isfinite(bd.Xmap[q])) finite = false;
-            }
-        int need = force ? 1 : 0;
-        for (int b = 0; b < nb && !need; ++b)
-            if (!(moved_bound(bodies[b], qmaps[b]) < margins[b] - kMarginSafety)) need = 1;
-        if (!finite) {
-            need = 0;
-            B.status = -4;
+// Decide whether the mapping must be redone and, if so, the box of cells to
+// scan: the union of every body's old and new bounding box plus two cells.
+// Called by the first wave, one lane per body; the lanes combine with wave
+// votes and min / max reductions, which do not depend on the order.
+__device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool force) {
+    const int nb = B.nb, b = threadIdx.x;
+    bool finite = true, need = false;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    if (b < nb) {
+        const DevBody &bd = sh.body[b];
+        // a body whose position is no longer finite cannot be mapped: the box
+        // is reported unstable and the flags stay as they are
+        for (int q = 0; q < 3; ++q)
+            if (!isfinite(bd.anchor[q] + bd.D[q]) || !isfinite(bd.Xmap[q])) finite = false;
+        need = !(moved_bound(bd, sh.qmap[b]) < sh.margin[b] - kMarginSafety);
+        const double ext = body_extent(bd);
+        for (int q = 0; q < 3; ++q) {
+            const double X = bd.anchor[q] + bd.D[q];
+            lo[q] = fmin(X, bd.Xmap[q]) - ext;
+            hi[q] = fmax(X, bd.Xmap[q]) + ext;
         }
-        B.map_req = need;
-        if (need) {
-            const int n[3] = {B.nx, B.ny, B.nz};
-            for (int q = 0; q < 3; ++q) {
-                double lo = 1e300, hi = -1e300;
-                for (int b = 0; b < nb; ++b) {
-                    const DevBody &bd = bodies[b];
-                    const double X = bd.anchor[q] + bd.D[q];
-                    const double e = body_extent(bd);
-                    lo = fmin(lo, fmin(X, bd.Xmap[q]) - e);
-                    hi = fmax(hi, fmax(X, bd.Xmap[q]) + e);
-                }
-                // clamp in double before converting, so that no integer overflows
-                lo = fmin(fmax(floor(lo) - 2.0, -4.0), (double)n[q] + 4.0);
-                hi = fmin(fmax(floor(hi) + 2.0, -4.0), (double)n[q] + 4.0);
-                int l = (int)lo, h = (int)hi;
-                if (nb == 0) { l = 0; h = -1; }
-                if (B.per & (1 << q)) {
-                    if (l < 0 || h >= n[q] || h - l + 1 >= n[q]) { l = 0; h = n[q] - 1; }
-                } else {
-                    l = max(l, 0);
-                    h = min(h, n[q] - 1);
-                }
-                B.map_lo[q] = l;
-                B.map_hi[q] = h;
-            }
+    }
+    const bool all_finite = !__any(!finite);
+    const bool any_need = force || __any(need);
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int q = 0; q < 3; ++q) {
+            lo[q] = fmin(lo[q], __shfl_xor(lo[q], m));
+            hi[q] = fmax(hi[q], __shfl_xor(hi[q], m));
         }
+    if (b != 0) return;
+    const int nmap = all_finite && any_need ? 1 : 0;
+    if (!all_finite) Bg.status = -4;
+    sh.map_req = nmap;
+    if (!nmap) return;
+    const int n[3] = {B.nx, B.ny, B.nz};
+    for (int q = 0; q < 3; ++q) {
+        // clamp in double before converting, so that no integer overflows
+        const double l0 = fmin(fmax(floor(lo[q]) - 2.0, -4.0), (double)n[q] + 4.0);
+        const double h0 = fmin(fmax(floor(hi[q]) + 2.0, -4.0), (double)n[q] + 4.0);
+        int l = (int)l0, h = (int)h0;
+        if (nb == 0) {
+            l = 0;
+            h = -1;
+        }
+        if (B.per & (1 << q)) {
+            if (l < 0 || h >= n[q] || h - l + 1 >= n[q]) {
+                l = 0;
+                h = n[q] - 1;
+            }
+        } else {
+            l = max(l, 0);
+            h = min(h, n[q] - 1);
+        }
+        sh.lo[q] = l;
+        sh.hi[q] = h;
     }
 }
 
@@ -418,15 +436,8 @@ __device__ void decide_map(BoxDesc &B, const DevBody *bodies, const double (*qma
 // one workgroup: new owners, body margins, refill of uncovered cells, then
 // near-body marks and the boundary links in cell order.
 template <typename S>
-__device__ void remap_box(BoxDesc &B, CoupleShared &sh, double *qmaps, double *margins) {
+__device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, double *qmaps, double *margins) {
     const int nb = B.nb;
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 3; ++q) {
-            sh.lo[q] = B.map_lo[q];
-            sh.hi[q] = B.map_hi[q];
-        }
-    }
-    __syncthreads();
     const int bx = sh.hi[0] - sh.lo[0] + 1, by = sh.hi[1] - sh.lo[1] + 1, bz = sh.hi[2] - sh.lo[2] + 1;
     const int ncell = (bx > 0 && by > 0 && bz > 0) ? bx * by * bz : 0;
     const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
@@ -551,9 +562,8 @@ __device__ void remap_box(BoxDesc &B, CoupleShared &sh, double *qmaps, double *m
         running += tot;
     }
     if (threadIdx.x == 0) {
-        B.link_count = running;
-        if (running > B.link_cap) B.status = -6;
-        B.map_req = 0;
+        Bg.link_count = running;
+        if (running > B.link_cap) Bg.status = -6;
     }
 }
 
@@ -564,16 +574,40 @@ __device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes
     for (int t = threadIdx.x; t < n; t += kCoupleThreads) ((int *)dst)[t] = ((const int *)src)[t];
 }
 
+// Stage the box's small tables in LDS: one pass over the words of all five
+// tables together, so that each thread issues its loads at once instead of
+// one table after the other.
 __device__ void stage_in(const BoxDesc &B, CoupleShared &sh, const double *qmaps, const double *margins) {
-    copy_words(sh.body, B.bodies, (int)sizeof(DevBody) * B.nb);
-    copy_words(sh.spring, B.springs, (int)sizeof(DevSpring) * B.ns);
-    copy_words(sh.drive, B.drives, (int)sizeof(DevDrive) * B.nd);
-    copy_words(sh.margin, margins, (int)sizeof(double) * B.nb);
-    copy_words(sh.qmap, qmaps, (int)sizeof(double) * 4 * B.nb);
+    const int n0 = (int)sizeof(DevBody) * B.nb / 4, n1 = (int)sizeof(DevSpring) * B.ns / 4;
+    const int n2 = (int)sizeof(DevDrive) * B.nd / 4, n3 = 2 * B.nb, n4 = 8 * B.nb;
+    const int total = n0 + n1 + n2 + n3 + n4;
+    for (int t = threadIdx.x; t < total; t += kCoupleThreads) {
+        int w = t;
+        const int *src;
+        int *dst;
+        if (w < n0) {
+            src = (const int *)B.bodies;
+            dst = (int *)sh.body;
+        } else if ((w -= n0) < n1) {
+            src = (const int *)B.springs;
+            dst = (int *)sh.spring;
+        } else if ((w -= n1) < n2) {
+            src = (const int *)B.drives;
+            dst = (int *)sh.drive;
+        } else if ((w -= n2) < n3) {
+            src = (const int *)margins;
+            dst = (int *)sh.margin;
+        } else {
+            w -= n3;
+            src = (const int *)qmaps;
+            dst = (int *)sh.qmap;
+        }
+        dst[w] = src[w];
+    }
     __syncthreads();
 }
 
-__device__ void stage_out(BoxDesc &B, CoupleShared &sh) {
+__device__ void stage_out(const BoxDesc &B, CoupleShared &sh) {
     __syncthreads();
     copy_words(B.bodies, sh.body, (int)sizeof(DevBody) * B.nb);
     __threadfence_block();
@@ -587,7 +621,10 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     __shared__ CoupleShared sh;
     const int bi = active[blockIdx.x / kRedBlocks];
     const int r = blockIdx.x % kRedBlocks;
-    BoxDesc &B = boxes[bi];
+    BoxDesc &Bg = boxes[bi];
+    // snapshot of the descriptor, taken before this kernel stores into it, so
+    // that no later read has to wait for those stores
+    const BoxDesc B = Bg;
     double *qm = qmaps + (size_t)bi * 4 * kMaxBodies;
     double *mg = margins + (size_t)bi * kMaxBodies;
     if (mode == kModeStep) {
@@ -605,15 +642,15 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         }
         stage_in(B, sh, qm, mg);
         finish_forces(B, sh);
-        rigid_step(B, sh);
+        rigid_step(B, Bg, sh);
     } else {
         if (r != 0) return;
         if (threadIdx.x == 0) sh.cur = B.cur;
         stage_in(B, sh, qm, mg);
     }
-    if (threadIdx.x == 0) decide_map(B, sh.body, sh.qmap, sh.margin, force_map || mode == kModeMapOnly);
+    if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
     stage_out(B, sh);
-    if (B.map_req) remap_box<S>(B, sh, qm, mg);
+    if (sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
 }
 
 }  // namespace lbm
