@@ -180,6 +180,49 @@ struct PushFast<S, 19, NT> {
                                                const typename Storage<S>::C *, float) {}
 };
 
+// Interior pushes with the x-shifted directions realigned across lanes.
+// The cells of a wave are consecutive, so the push of lane l along +x lands
+// on lane l+1's cell: if lane l+1 holds the next cell of the same row, lane
+// l+1 stores the value it received from lane l at its own, aligned slot
+// (from_left); lane l stores it itself only where no neighbour takes it
+// (own_px), that is at the end of a row or a wave or next to a cell on the
+// general path.  -x works the same way from the right.  Every destination is
+// still written exactly once, with the same value.
+struct XLanes {
+    bool from_left, from_right, own_px, own_mx, fast;
+};
+
+template <typename S, int A, bool NT>
+struct PushLanes {
+    template <typename P>
+    static __device__ __forceinline__ void run(P dst, long long stride, int cell, const int *off_p,
+                                               const int *off_m, const typename Storage<S>::C *f, float scale,
+                                               const XLanes &x) {
+        using St = Storage<S>;
+        const int oyz = (ey(A) > 0 ? off_p[1] : ey(A) < 0 ? off_m[1] : 0) +
+                        (ez(A) > 0 ? off_p[2] : ez(A) < 0 ? off_m[2] : 0);
+        P base = dst + (size_t)A * stride;
+        if constexpr (ex(A) == 0) {
+            if (x.fast) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), f[A], scale);
+        } else if constexpr (ex(A) > 0) {
+            const auto v = __shfl_up(f[A], 1);
+            if (x.from_left) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), v, scale);
+            if (x.own_px) St::template store<NT>(base, (size_t)(unsigned)(cell + off_p[0] + oyz), f[A], scale);
+        } else {
+            const auto v = __shfl_down(f[A], 1);
+            if (x.from_right) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), v, scale);
+            if (x.own_mx) St::template store<NT>(base, (size_t)(unsigned)(cell + off_m[0] + oyz), f[A], scale);
+        }
+        PushLanes<S, A + 1, NT>::run(dst, stride, cell, off_p, off_m, f, scale, x);
+    }
+};
+template <typename S, bool NT>
+struct PushLanes<S, 19, NT> {
+    template <typename P>
+    static __device__ __forceinline__ void run(P, long long, int, const int *, const int *,
+                                               const typename Storage<S>::C *, float, const XLanes &) {}
+};
+
 // Map a workgroup to its tile.  With xcd_order, the hardware's round-robin
 // placement of consecutive workgroups on the 8 XCDs is undone so that each
 // XCD sweeps one contiguous slab of tiles (neighbouring rows share its L2).
@@ -200,17 +243,24 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
     const WorkItem wk = work[t];
     const BoxDesc &B = boxes[wk.box];
     const int cell = wk.first + (int)threadIdx.x;
-    if (cell >= B.N) return;
-    const uint8_t fl = B.flags[cell];
-    if (fl & kOwnerMask) return;  // inside a body: no fluid
+    // every lane stays until the interior stores are done: the x-shifted
+    // pushes are exchanged between neighbouring lanes
+    const bool valid = cell < B.N;
+    const uint8_t fl = valid ? B.flags[cell] : kOwnerMask;
+    const bool fluid = !(fl & kOwnerMask);  // a body cell has no fluid
     const long long stride = B.stride;
     // the population buffers live in global memory: say so, so that the
     // loads and stores of the interior path are global, not flat
     const global_t<S> *src = (const global_t<S> *)(B.cur ? B.pop1 : B.pop0);
     global_t<S> *dst = (global_t<S> *)(B.cur ? B.pop0 : B.pop1);
     C f[19];
+    if (fluid) {
 #pragma unroll
-    for (int a = 0; a < 19; ++a) f[a] = St::template load<NT>(src, (size_t)a * stride + cell, B.inv_scale);
+        for (int a = 0; a < 19; ++a) f[a] = St::template load<NT>(src, (size_t)a * stride + cell, B.inv_scale);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 19; ++a) f[a] = C(0);
+    }
     // coordinates from the tile origin (no integer division)
     int i = wk.i0 + (int)threadIdx.x, j = wk.j0, k = wk.k0;
     while (i >= B.nx) {
@@ -237,11 +287,29 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
         off_m[a] = at_lo[a] ? (len[a] - 1) * span[a] : -span[a];
         wall |= !p && (at_lo[a] || at_hi[a]);
     }
-    if (!wall && !(fl & kNearBit)) {
-        St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
-        PushFast<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale);
-        return;
+    const bool fast = valid && fluid && !wall && !(fl & kNearBit);
+    if constexpr (sizeof(S) >= 4) {
+        // 4- and 8-byte storage: realign the x-shifted pushes across lanes
+        // (2% faster on the 256x128x128 box; the 2-byte formats gain nothing)
+        const int lane = (int)threadIdx.x & 63;
+        XLanes x;
+        x.fast = fast;
+        const bool left_fast = __shfl_up((int)fast, 1) != 0, right_fast = __shfl_down((int)fast, 1) != 0;
+        const bool left_row = lane >= 1 && i != 0, right_row = lane <= 62 && i != nx - 1;
+        x.from_left = valid && left_row && left_fast;
+        x.from_right = valid && right_row && right_fast;
+        x.own_px = fast && !(right_row && right_fast);
+        x.own_mx = fast && !(left_row && left_fast);
+        if (fast) St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
+        PushLanes<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale, x);
+    } else {
+        // 2-byte storage: each lane pushes its own values
+        if (fast) {
+            St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
+            PushFast<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale);
+        }
     }
+    if (fast || !valid || !fluid) return;
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
     St::store(gdst, (size_t)cell, f[0], B.scale);
     int nlink = 0;
