@@ -110,7 +110,7 @@ typedef struct {
                                  lbm_set_bodies).  The paper does not say; the
                                  mean removes the period-2 mode that the explicit
                                  coupling amplifies for tau < 1.  lbm_adjoint
-                                 rejects 1. */
+                                 differentiates either form. */
     int32_t reserved;         /* must be 0 */
 } lbm_params;
 

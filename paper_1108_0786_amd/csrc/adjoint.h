@@ -29,6 +29,10 @@ struct AdjBody {
     double lF[3], lT[3];            // adjoints of the hydrodynamic force / torque of step n
     double muV[3];                  // adjoint of V^{n+1} including its use in D^{n+1}
     double lDs[3], lVs[3];          // spring contributions to lam_D^n, lam_V^n
+    // with the two-step force mean: the plain adjoints of the force and torque
+    // of step n+1 (the hydrodynamic sums of step n move the bodies at steps n
+    // and n+1, half each)
+    double lFn[3], lTn[3];
 };
 
 // body state of one step kept for the reverse pass
@@ -275,6 +279,17 @@ __global__ __launch_bounds__(kCoupleThreads) void adjoint_body_kernel(const BoxD
                 bt[p] = bd.kinematic != 0 ? 0.0
                                      : (R[0][p] * ab.lO[0] + R[1][p] * ab.lO[1] + R[2][p] * ab.lO[2]) / bd.inertia[p];
             for (int p = 0; p < 3; ++p) ab.lT[p] = R[p][0] * bt[0] + R[p][1] * bt[1] + R[p][2] * bt[2];
+            if (B.force_avg) {
+                // the hydrodynamic force and torque of step n enter the updates of
+                // steps n and n+1 with weight 1/2 each
+                for (int q = 0; q < 3; ++q) {
+                    const double f = ab.lF[q], t = ab.lT[q];
+                    ab.lF[q] = 0.5 * (f + ab.lFn[q]);
+                    ab.lT[q] = 0.5 * (t + ab.lTn[q]);
+                    ab.lFn[q] = f;
+                    ab.lTn[q] = t;
+                }
+            }
             grad[0] += lF[b][0] * dFa[b];
             grad[1] += lF[b][0] * dFp[b];
         }

@@ -578,6 +578,7 @@ __global__ void init_adjoint_kernel(AdjBody *adj, const double *w, int nb, doubl
     for (int q = 0; q < 3; ++q) {
         a.lD[q] = w[3 * b + q];
         a.lV[q] = a.lO[q] = a.lF[q] = a.lT[q] = a.muV[q] = a.lDs[q] = a.lVs[q] = 0.0;
+        a.lFn[q] = a.lTn[q] = 0.0;
     }
 }
 
@@ -724,8 +725,6 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
         return fail(c, LBM_E_ARG, "nsteps and checkpoint_every must be >= 1; outputs must be non-null");
     if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
     if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
-    if (c->boxes[0].p.force_average)
-        return fail(c, LBM_E_ARG, "the adjoint covers the plain explicit coupling (force_average = 0)");
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         return adjoint_impl<S>(c, nsteps, checkpoint_every, dJ_ddisp, J, grad);

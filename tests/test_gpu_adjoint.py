@@ -47,11 +47,14 @@ def _gpu_J(case, storage):
     return J
 
 
-def test_adjoint_matches_oracle_complex_step_tiny():
+@pytest.mark.parametrize("average", [False, True])
+def test_adjoint_matches_oracle_complex_step_tiny(average):
+    # plain explicit coupling and the two-step force mean
     from paper_1108_0786_amd.sim import Sim
     case = _tiny()
+    case.force_average = average
     base = {"amplitude": 5e-3, "phase_lag": 1.1, "k": 0.05}
-    print(f"[gpu] adjoint tiny {case.name} {case.steps} steps", flush=True)
+    print(f"[gpu] adjoint tiny {case.name} {case.steps} steps, force mean {average}", flush=True)
     sim = Sim(case, storage="f64")
     J, grad = sim.adjoint(case.steps, checkpoint_every=7)
     sim.close()

@@ -226,11 +226,3 @@ def test_force_average_fp64_parity():
     print(f"[gpu] force average errors F {eF:.2e} D {eD:.2e} dF {eP:.2e}", flush=True)
     assert eF < 1e-12 and eD < 1e-12 and eP < 1e-12
     sim.close()
-
-
-def test_adjoint_rejects_force_average():
-    from paper_1108_0786_amd._abi import LbmError
-    sim = _sim(_averaged_case(steps=10), storage="f64")
-    with pytest.raises(LbmError):
-        sim.adjoint(10)
-    sim.close()
