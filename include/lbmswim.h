@@ -158,8 +158,9 @@ int lbm_init(const lbm_params *params, lbm_ctx **out);
 int lbm_init_batch(const lbm_params *params, int32_t nbox, lbm_ctx **out);
 
 /* Set the bodies, springs and driving protocols of box 0 (lbm_set_bodies)
- * or of box `box`, and map them onto the lattice (Sec. 2.3).  Bodies must not
- * overlap each other or reach a wall (LBM_E_OVERLAP); indices must be in
+ * or of box `box`, and map them onto the lattice (Sec. 2.3).  Bodies must keep
+ * at least one cell between their surfaces and from the walls, measured on
+ * the exact sphere and capsule shapes (LBM_E_OVERLAP); indices must be in
  * range (LBM_E_ARG).  On a box that already holds bodies, cells that leave a
  * body are refilled as in a step. */
 int lbm_set_bodies(lbm_ctx *ctx, const lbm_body *bodies, int32_t nb,

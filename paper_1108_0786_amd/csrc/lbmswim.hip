@@ -234,6 +234,53 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
 
 double body_extent_h(const lbm_body &b) { return b.radius + (b.shape == LBM_CAPSULE ? b.half_len : 0.0); }
 
+// Half axis of a body's core segment in world axes: R(quat) (h, 0, 0), zero
+// for a sphere.
+void core_half_axis(const lbm_body &b, double a[3]) {
+    const double h = b.shape == LBM_CAPSULE ? b.half_len : 0.0;
+    const double w = b.quat[0], x = b.quat[1], y = b.quat[2], z = b.quat[3];
+    a[0] = h * (1 - 2 * (y * y + z * z));
+    a[1] = h * 2 * (x * y + w * z);
+    a[2] = h * 2 * (x * z - w * y);
+}
+
+// Squared distance between the segments p + s d and q + t e, s, t in [0, 1]:
+// minimise over s and t, clamping to the segment ends.
+double segment_distance2(const double p[3], const double d[3], const double q[3], const double e[3]) {
+    auto dot = [](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+    auto clamp01 = [](double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); };
+    const double r[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+    const double aa = dot(d, d), ee = dot(e, e), f = dot(e, r), tiny = 1e-300;
+    double s = 0.0, t = 0.0;
+    if (aa <= tiny && ee <= tiny) {
+        s = t = 0.0;
+    } else if (aa <= tiny) {
+        t = clamp01(f / ee);
+    } else {
+        const double c = dot(d, r);
+        if (ee <= tiny) {
+            s = clamp01(-c / aa);
+        } else {
+            const double b = dot(d, e), den = aa * ee - b * b;
+            s = den > 0.0 ? clamp01((b * f - c * ee) / den) : 0.0;
+            t = (b * s + f) / ee;
+            if (t < 0.0) {
+                t = 0.0;
+                s = clamp01(-c / aa);
+            } else if (t > 1.0) {
+                t = 1.0;
+                s = clamp01((b - c) / aa);
+            }
+        }
+    }
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double v = (p[k] + s * d[k]) - (q[k] + t * e[k]);
+        d2 += v * v;
+    }
+    return d2;
+}
+
 int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb,
                     const lbm_spring *springs, int ns, const lbm_drive *drives, int nd) {
     if (nb < 0 || nb > kMaxBodies) return fail(c, LBM_E_ARG, "between 0 and 16 bodies per box");
@@ -250,28 +297,36 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
         if (B.kinematic == 0 && !(B.inertia[0] > 0 && B.inertia[1] > 0 && B.inertia[2] > 0))
             return fail(c, LBM_E_ARG, "body inertia must be positive");
         const double e = body_extent_h(B);
-        for (int q = 0; q < 3; ++q) {
-            const double X = B.anchor[q] + B.disp[q];
-            if (!std::isfinite(X)) return fail(c, LBM_E_ARG, "body position not finite");
-            if (h.p.periodic_mask & (1u << q)) {
-                if (2.0 * e + 4.0 >= n[q]) return fail(c, LBM_E_ARG, "body too large for the periodic box");
-            } else if (X - e < 1.0 || X + e > n[q] - 1.0) {
-                return fail(c, LBM_E_OVERLAP, "body reaches a wall (keep one cell of fluid)");
-            }
-        }
         const double qn = std::sqrt(B.quat[0] * B.quat[0] + B.quat[1] * B.quat[1] + B.quat[2] * B.quat[2] +
                                     B.quat[3] * B.quat[3]);
         if (std::fabs(qn - 1.0) > 1e-6) return fail(c, LBM_E_ARG, "quaternion must be normalised");
+        double ax[3];
+        core_half_axis(B, ax);
+        for (int q = 0; q < 3; ++q) {
+            const double X = B.anchor[q] + B.disp[q];
+            const double eq = B.radius + std::fabs(ax[q]);   // extent along axis q
+            if (!std::isfinite(X)) return fail(c, LBM_E_ARG, "body position not finite");
+            if (h.p.periodic_mask & (1u << q)) {
+                if (2.0 * e + 4.0 >= n[q]) return fail(c, LBM_E_ARG, "body too large for the periodic box");
+            } else if (X - eq < 1.0 || X + eq > n[q] - 1.0) {
+                return fail(c, LBM_E_OVERLAP, "body reaches a wall (keep one cell of fluid)");
+            }
+        }
         for (int o = 0; o < b; ++o) {
             const lbm_body &O = bodies[o];
-            double d2 = 0;
+            // core segments, the other body moved to its nearest periodic image
+            double ao[3], p0[3], d0[3], p1[3], d1[3];
+            core_half_axis(O, ao);
             for (int q = 0; q < 3; ++q) {
                 double d = (B.anchor[q] + B.disp[q]) - (O.anchor[q] + O.disp[q]);
                 if (h.p.periodic_mask & (1u << q)) d -= n[q] * std::nearbyint(d / n[q]);
-                d2 += d * d;
+                p0[q] = d - ax[q];
+                d0[q] = 2.0 * ax[q];
+                p1[q] = -ao[q];
+                d1[q] = 2.0 * ao[q];
             }
-            // bounding spheres plus one cell of fluid between the bodies
-            if (std::sqrt(d2) < body_extent_h(B) + body_extent_h(O) + 1.0)
+            // one cell of fluid between the surfaces
+            if (std::sqrt(segment_distance2(p0, d0, p1, d1)) < B.radius + O.radius + 1.0)
                 return fail(c, LBM_E_OVERLAP, "bodies overlap (or touch)");
         }
     }

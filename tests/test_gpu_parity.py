@@ -226,3 +226,25 @@ def test_force_average_fp64_parity():
     print(f"[gpu] force average errors F {eF:.2e} D {eD:.2e} dF {eP:.2e}", flush=True)
     assert eF < 1e-12 and eD < 1e-12 and eP < 1e-12
     sim.close()
+
+
+def test_capsule_clearance_uses_the_exact_shape():
+    # capsules r = 4, cylinder 8, 16 cells apart: side by side (axes along y)
+    # they leave 8 cells of fluid; end to end (axes along x) they touch
+    from paper_1108_0786_amd._abi import LBM_E_OVERLAP, LbmError
+    c45 = math.sqrt(0.5)
+
+    def pair(quat, y=24.0):
+        bodies = [W.make_body(W.CAPSULE, 4.0, 400.0, (24.0 + 16.0 * n, y, 24.0), 4.0, quat=quat) for n in range(2)]
+        return W.Case("pair", 64, 48, 48, 0.8, bodies=bodies, steps=1)
+
+    print("[gpu] capsule clearance", flush=True)
+    _sim(pair((c45, 0.0, 0.0, c45)), storage="f32").close()
+    with pytest.raises(LbmError) as e:
+        _sim(pair((1.0, 0.0, 0.0, 0.0)), storage="f32")
+    assert e.value.code == LBM_E_OVERLAP
+    # across the channel the capsule reaches y +- 8: one cell from the wall at 9, not at 8.5
+    _sim(pair((c45, 0.0, 0.0, c45), y=9.0), storage="f32").close()
+    with pytest.raises(LbmError) as e:
+        _sim(pair((c45, 0.0, 0.0, c45), y=8.5), storage="f32")
+    assert e.value.code == LBM_E_OVERLAP

@@ -283,6 +283,30 @@ def paper_design(design: str = "a", storage: str = "f64") -> Case:
                 steps=196812, storage=storage, force_average=True)
 
 
+def paper_capsule_design(design: str = "f", storage: str = "f64") -> Case:
+    """The all-capsule swimmers of the Sec. 5.1 design study, in the channel of
+    ``paper_design``: (f) three capsules along the swimmer axis, surface gaps
+    8; (k) three capsules across it (axis along y), gaps 16; (p) the same
+    with gaps 8.  Capsules of radius 4 and length 16 (cylinder 8) with the
+    spheres' mass, rotation locked, moved with the two-step force mean."""
+    r, h = 4.0, 4.0
+    m, k, gamma, a = paper_units()
+    T = PAPER_SI["period"]
+    across = design in ("k", "p")
+    gap = {"f": 8.0, "k": 16.0, "p": 8.0}[design]
+    l0 = gap + 2.0 * (r if across else r + h)
+    b, s, d = swimmer((100.0, 50.0, 50.0), shapes=(CAPSULE, CAPSULE, CAPSULE), r=r, h=h, l0=(l0, l0), k=k,
+                      gamma=gamma, mass=m, amplitude=a, period=float(T), phase_lag=math.pi / 2, gate_lagged=True,
+                      off_left=5 * T, off_right=5 * T + T // 4)
+    c45 = math.sqrt(0.5)
+    for body in b:
+        body.kinematic = 2
+        if across:
+            body.quat = (c45, 0.0, 0.0, c45)   # body x axis turned onto y
+    return Case(f"paper_{design}_200x100x100", 200, 100, 100, 2.0 / 3.0, bodies=b, springs=s, drives=[d],
+                steps=196812, storage=storage, force_average=True)
+
+
 def random_small(seed: int, storage: str = "f64") -> Case:
     """A small random box with one to three free, kinematic or rotation-locked
     spheres/capsules,
