@@ -73,7 +73,8 @@ enum {
     LBM_E_OVERLAP = -3,   /* bodies overlap each other or a wall */
     LBM_E_UNSTABLE = -4,  /* a body force or state became non-finite */
     LBM_E_STATE = -5,     /* call not valid in the current state */
-    LBM_E_CAPACITY = -6   /* link list exceeded its capacity */
+    LBM_E_CAPACITY = -6,  /* link list exceeded its capacity */
+    LBM_E_SYNC = -7       /* the coupling kernel's workgroups timed out at a barrier */
 };
 
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
@@ -212,7 +213,10 @@ int lbm_import_populations(lbm_ctx *ctx, int32_t box, const double *src);
 int lbm_step_count(lbm_ctx *ctx, int32_t box, int64_t *steps);
 
 /* Synchronise and report a device-side failure: LBM_E_UNSTABLE if a body
- * force or state became non-finite, LBM_E_CAPACITY if a link list overflowed. */
+ * force or state became non-finite, LBM_E_CAPACITY if a link list overflowed,
+ * LBM_E_SYNC if the workgroups of a cooperative mapping (LBM_TUNE_COOP_REMAP)
+ * waited at a barrier for longer than about a second (they then give up, so
+ * that the kernel always ends; the box's state is not valid afterwards). */
 int lbm_status(lbm_ctx *ctx);
 
 /* Hand-written reverse mode (adjoint) of nsteps coupled steps of box 0 of a
@@ -243,9 +247,14 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *                         have changed side (default 0; results are identical)
  *   LBM_TUNE_NONTEMPORAL  1: streaming (non-temporal) loads and stores in the
  *                         sweep's interior path (default 1 for LBM_F16S and
- *                         LBM_BF16S, 0 otherwise) */
+ *                         LBM_BF16S, 0 otherwise)
+ *   LBM_TUNE_COOP_REMAP   1 (default): when every workgroup of the coupling
+ *                         launch can be resident at once (up to the device's
+ *                         occupancy for it: a few boxes per launch), all
+ *                         workgroups of a box share its mapping; 0: one
+ *                         workgroup maps each box.  Results are identical. */
 enum { LBM_TUNE_BLOCK = 0, LBM_TUNE_XCD_ORDER = 1, LBM_TUNE_GRAPH_STEPS = 2, LBM_TUNE_FULL_REMAP = 3,
-       LBM_TUNE_NONTEMPORAL = 4 };
+       LBM_TUNE_NONTEMPORAL = 4, LBM_TUNE_COOP_REMAP = 5 };
 int lbm_tune(lbm_ctx *ctx, int32_t key, int64_t value);
 
 /* Kernel timing.  With enable = 1, lbm_step launches every kernel itself (no

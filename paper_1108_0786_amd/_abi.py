@@ -6,11 +6,12 @@ import os
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblbmswim.so")
 
-LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_OVERLAP, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_CAPACITY = 0, -1, -2, -3, -4, -5, -6
+LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_OVERLAP, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_CAPACITY, LBM_E_SYNC = \
+    0, -1, -2, -3, -4, -5, -6, -7
 ERROR_NAMES = {-1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_OVERLAP", -4: "LBM_E_UNSTABLE",
-               -5: "LBM_E_STATE", -6: "LBM_E_CAPACITY"}
+               -5: "LBM_E_STATE", -6: "LBM_E_CAPACITY", -7: "LBM_E_SYNC"}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
-TUNE = {"block": 0, "xcd_order": 1, "graph_steps": 2, "full_remap": 3, "nontemporal": 4}
+TUNE = {"block": 0, "xcd_order": 1, "graph_steps": 2, "full_remap": 3, "nontemporal": 4, "coop_remap": 5}
 TRAJ_DOUBLES = 16
 
 SYMBOLS = [

@@ -177,7 +177,7 @@ struct BoxDesc {
     double *traj;
     long long traj_cap;
     void *partials;            // momentum-exchange partial sums, one slice per reduction workgroup
-    int *counter;              // reduction workgroups of the current step that have finished
+    void *ctl;                 // control words of the coupling kernel (counter, barrier, remap slices)
     // mutable state, advanced on the device
     long long step;
     int cur;                   // index of the buffer holding the current populations

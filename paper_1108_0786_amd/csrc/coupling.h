@@ -7,10 +7,12 @@
 //      block order, adds the driving forces (Eqs. FB1-FB3) and the
 //      spring-damper forces (Eqs. osci_i/j) and advances every body by one
 //      semi-implicit Euler step (Alg. 1);
-//   3. the same workgroup maps the bodies for the next step (Sec. 2.3): new
-//      flags, refill of uncovered cells, near-body marks and the boundary
-//      links, skipped when no cell can have changed side since the last
-//      mapping.
+//   3. the bodies are mapped for the next step (Sec. 2.3): new flags, refill
+//      of uncovered cells, near-body marks and the boundary links, skipped
+//      when no cell can have changed side since the last mapping.  When all
+//      workgroups of the launch can be resident at once, the box's
+//      kRedBlocks workgroups wait for the decision and share the mapping
+//      (cooperative); otherwise the finishing workgroup maps alone.
 // All sums are in a fixed order, so results do not depend on which
 // workgroup finishes last.
 #pragma once
@@ -24,8 +26,21 @@ constexpr int kMaxBodies = 16;
 constexpr int kMaxSprings = 64;
 constexpr int kMaxDrives = 16;
 constexpr double kMarginSafety = 1e-9;
+constexpr int kSpinLimit = 1 << 20;   // polls of a workgroup barrier before it gives up (about a second)
 
 enum : int { kModeStep = 0, kModeMapOnly = 1 };
+
+// Control words of one box's coupling launch, in device memory, zeroed when
+// the box is set up.
+struct CoupleCtl {
+    int counter;                 // reduction workgroups of the current step that have finished
+    unsigned arrived, gen;       // barrier of the box's workgroups: arrivals, generation
+    int map_req, cur;            // published by the finishing workgroup: remap needed, buffer index
+    int share;                   // set by the last step: this step's workgroups stay to share a remap
+    int lo[3], hi[3];            // ... and the cell box to map
+    int counts[kRedBlocks];      // links found in each workgroup's slice of the cell box
+    unsigned long long margin[kMaxBodies];  // bits of each body's margin (a non-negative double)
+};
 
 // partial momentum-exchange sums of one body over one slice of the links:
 // F (3), T (3) in double; S (3), G (3) exact integers
@@ -46,6 +61,11 @@ struct CoupleShared {
     int lo[3], hi[3];          // cell box the remap scans (when map_req)
     int map_req;               // 1: this step ends with a remap
     int last;
+    int sync_ok;               // 0: a barrier of the cooperative remap timed out
+    int first;                 // number of the first link of this workgroup's slice
+    int share_next;            // the next step may remap: its workgroups should stay
+    int rcount;                // cells to refill found in the current round
+    int rlist[kCoupleThreads];
     int cur;                   // index of the current population buffer
     // the box's small tables, staged in LDS by the workgroup that finishes the step
     DevBody body[kMaxBodies];
@@ -380,7 +400,7 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
 // votes and min / max reductions, which do not depend on the order.
 __device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool force) {
     const int nb = B.nb, b = threadIdx.x;
-    bool finite = true, need = false;
+    bool finite = true, need = false, soon = false;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     if (b < nb) {
         const DevBody &bd = sh.body[b];
@@ -388,7 +408,16 @@ __device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool
         // is reported unstable and the flags stay as they are
         for (int q = 0; q < 3; ++q)
             if (!isfinite(bd.anchor[q] + bd.D[q]) || !isfinite(bd.Xmap[q])) finite = false;
-        need = !(moved_bound(bd, sh.qmap[b]) < sh.margin[b] - kMarginSafety);
+        const double moved = moved_bound(bd, sh.qmap[b]);
+        need = !(moved < sh.margin[b] - kMarginSafety);
+        // may the next step need a remap: two more steps at the present
+        // speeds (only decides whether the next step's workgroups stay to
+        // share the work; see couple_kernel)
+        double ahead = moved + 2.0 * sqrt(bd.V[0] * bd.V[0] + bd.V[1] * bd.V[1] + bd.V[2] * bd.V[2]) + 1e-6;
+        if (bd.shape == kBodyShapeCapsule)
+            ahead += 2.0 * sqrt(bd.O[0] * bd.O[0] + bd.O[1] * bd.O[1] + bd.O[2] * bd.O[2]) *
+                     (bd.half_len + bd.radius + 2.0);
+        soon = !(ahead < sh.margin[b] - kMarginSafety);
         const double ext = body_extent(bd);
         for (int q = 0; q < 3; ++q) {
             const double X = bd.anchor[q] + bd.D[q];
@@ -398,6 +427,7 @@ __device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool
     }
     const bool all_finite = !__any(!finite);
     const bool any_need = force || __any(need);
+    const bool any_soon = __any(soon);
     for (int m = 32; m >= 1; m >>= 1)
         for (int q = 0; q < 3; ++q) {
             lo[q] = fmin(lo[q], __shfl_xor(lo[q], m));
@@ -407,6 +437,7 @@ __device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool
     const int nmap = all_finite && any_need ? 1 : 0;
     if (!all_finite) Bg.status = -4;
     sh.map_req = nmap;
+    sh.share_next = nmap || any_soon;
     if (!nmap) return;
     const int n[3] = {B.nx, B.ny, B.nz};
     for (int q = 0; q < 3; ++q) {
@@ -432,18 +463,38 @@ __device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool
     }
 }
 
-// The object mapping (Sec. 2.3) over the cell box chosen by decide_map, by
-// one workgroup: new owners, body margins, refill of uncovered cells, then
-// near-body marks and the boundary links in cell order.
-template <typename S>
-__device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, double *qmaps, double *margins) {
-    const int nb = B.nb;
-    const int bx = sh.hi[0] - sh.lo[0] + 1, by = sh.hi[1] - sh.lo[1] + 1, bz = sh.hi[2] - sh.lo[2] + 1;
-    const int ncell = (bx > 0 && by > 0 && bz > 0) ? bx * by * bz : 0;
-    const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
-    // pass 1: new owners; remember the old ones
-    for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
-        const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
+// The object mapping (Sec. 2.3) over the cell box chosen by decide_map.  The
+// box is scanned as a linear range of cells t = 0 .. bx*by*bz - 1 (x fastest);
+// each pass below covers a slice [t0, t1) of it, the whole range when one
+// workgroup maps the box, one contiguous slice per workgroup when all
+// kRedBlocks workgroups of the box take part.  Body data come from the
+// workgroup's LDS copy (sh.body).
+struct MapBox {
+    int lo[3], bx, by, ncell;
+};
+
+__device__ __forceinline__ MapBox map_box(const CoupleShared &sh) {
+    MapBox m;
+    for (int q = 0; q < 3; ++q) m.lo[q] = sh.lo[q];
+    m.bx = sh.hi[0] - sh.lo[0] + 1;
+    m.by = sh.hi[1] - sh.lo[1] + 1;
+    const int bz = sh.hi[2] - sh.lo[2] + 1;
+    m.ncell = (m.bx > 0 && m.by > 0 && bz > 0) ? m.bx * m.by * bz : 0;
+    return m;
+}
+
+__device__ __forceinline__ void map_cell(const MapBox &m, int t, int &i, int &j, int &k) {
+    i = m.lo[0] + t % m.bx;
+    j = m.lo[1] + (t / m.bx) % m.by;
+    k = m.lo[2] + t / (m.bx * m.by);
+}
+
+// pass 1: new owners; remember the old ones
+__device__ void map_owners(const BoxDesc &B, const CoupleShared &sh, const MapBox &m, int t0, int t1) {
+    const int nb = B.nb, nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kCoupleThreads) {
+        int i, j, k;
+        map_cell(m, t, i, j, k);
         const int c = i + nx * (j + ny * k);
         if (c < 0 || c >= B.N) continue;
         const uint8_t old = B.flags[c] & kOwnerMask;
@@ -451,91 +502,143 @@ __device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, doubl
         for (int b = nb - 1; b >= 0; --b) {
             double r[3];
             int d[3];
-            lever_arm(B.bodies[b], i, j, k, nx, ny, nz, per, r, d);
-            if (inside(B.bodies[b], r)) owner = b + 1;
+            lever_arm(sh.body[b], i, j, k, nx, ny, nz, per, r, d);
+            if (inside(sh.body[b], r)) owner = b + 1;
         }
         B.old_owner[c] = old;
         B.flags[c] = (uint8_t)owner;
     }
-    // margin of every body: the smallest distance of a scanned cell centre
-    // from its surface; until the body has moved that far no cell changes side
-    for (int b = 0; b < nb; ++b) {
-        double m = 1e300;
-        const DevBody &bd = B.bodies[b];
-        for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
-            const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
-            double r[3];
+}
+
+// this thread's part of the margin of body b over the slice: the smallest
+// distance of a scanned cell centre from the body's surface; until the body
+// has moved that far no cell changes side
+__device__ double map_margin(const BoxDesc &B, const DevBody &bd, const MapBox &m, int t0, int t1) {
+    double mm = 1e300;
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kCoupleThreads) {
+        int i, j, k;
+        map_cell(m, t, i, j, k);
+        double r[3];
+        int d[3];
+        lever_arm(bd, i, j, k, B.nx, B.ny, B.nz, B.per, r, d);
+        mm = fmin(mm, fabs(sqrt(core_dist2(bd, r)) - bd.radius));
+    }
+    return mm;
+}
+
+// pass 2: refill cells that left a body (equilibrium at the body's velocity,
+// density averaged over neighbours that are fluid before and after); needs
+// pass 1 done on the neighbours.  The cells to refill are gathered first;
+// then one wave refills each, lane a loading the 19 populations of the
+// neighbour in direction a, and lane q storing direction q.  The sums run in
+// the order one thread would take (directions ascending), so the result
+// does not depend on the gathering order.
+template <typename S>
+__device__ void map_refill(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int cur) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
+    void *popc = cur ? B.pop1 : B.pop0;
+    const size_t stride = (size_t)B.stride;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = t0; base < t1; base += kCoupleThreads) {
+        __syncthreads();
+        if (threadIdx.x == 0) sh.rcount = 0;
+        __syncthreads();
+        const int t = base + (int)threadIdx.x;
+        if (t < t1) {
+            int i, j, k;
+            map_cell(m, t, i, j, k);
+            const int c = i + nx * (j + ny * k);
+            if (c >= 0 && c < B.N && B.old_owner[c] != 0 && (B.flags[c] & kOwnerMask) == 0)
+                sh.rlist[atomicAdd(&sh.rcount, 1)] = c;
+        }
+        __syncthreads();
+        const int n = sh.rcount;
+        for (int e = wave; e < n; e += kCoupleThreads / 64) {
+            const int c = sh.rlist[e];
+            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            double s = 0.0;
+            int valid = 0;
+            if (lane >= 1 && lane < 19) {
+                int ti, tj, tk;
+                if (neighbour_rt(lane, i, j, k, nx, ny, nz, per, ti, tj, tk)) {
+                    const int nc = ti + nx * (tj + ny * tk);
+                    if (B.old_owner[nc] == 0 && (B.flags[nc] & kOwnerMask) == 0) {
+                        valid = 1;
+                        double v[19];
+#pragma unroll
+                        for (int q = 0; q < 19; ++q) v[q] = load_dev<S>(popc, (size_t)q * stride + nc, B.inv_scale);
+                        s = v[0];
+#pragma unroll
+                        for (int q = 1; q < 19; ++q) s = s + v[q];
+                    }
+                }
+            }
+            double total = 0.0;
+            int count = 0;
+            for (int a = 1; a < 19; ++a) {
+                const double sa = __shfl(s, a, 64);
+                if (__shfl(valid, a, 64)) {
+                    total = total + sa;
+                    ++count;
+                }
+            }
+            const double drho = count ? total / (double)count : 0.0;
+            const double rho = 1.0 + drho;
+            const DevBody &bd = sh.body[B.old_owner[c] - 1];
+            double r[3], u[3];
             int d[3];
             lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
-            m = fmin(m, fabs(sqrt(core_dist2(bd, r)) - bd.radius));
-        }
-        m = block_min(m, sh);
-        if (threadIdx.x == 0) {
-            margins[b] = m;
-            for (int q = 0; q < 3; ++q) B.bodies[b].Xmap[q] = B.bodies[b].anchor[q] + B.bodies[b].D[q];
-            for (int q = 0; q < 4; ++q) qmaps[4 * b + q] = B.bodies[b].q[q];
-        }
-    }
-    __threadfence_block();
-    __syncthreads();
-    // pass 2: refill cells that left a body (equilibrium at the body's velocity,
-    // density averaged over neighbours that are fluid before and after)
-    void *popc = sh.cur ? B.pop1 : B.pop0;
-    const size_t stride = (size_t)B.stride;
-    for (int t = threadIdx.x; t < ncell; t += kCoupleThreads) {
-        const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
-        const int c = i + nx * (j + ny * k);
-        if (c < 0 || c >= B.N) continue;
-        const int old = B.old_owner[c];
-        if (old == 0 || (B.flags[c] & kOwnerMask) != 0) continue;
-        double total = 0.0;
-        int count = 0;
-        for (int a = 1; a < 19; ++a) {
-            int ti, tj, tk;
-            if (!neighbour_rt(a, i, j, k, nx, ny, nz, per, ti, tj, tk)) continue;
-            const int nc = ti + nx * (tj + ny * tk);
-            if (B.old_owner[nc] != 0 || (B.flags[nc] & kOwnerMask) != 0) continue;
-            double s = load_dev<S>(popc, nc, B.inv_scale);
-            for (int q = 1; q < 19; ++q) s = s + load_dev<S>(popc, (size_t)q * stride + nc, B.inv_scale);
-            total = total + s;
-            ++count;
-        }
-        const double drho = count ? total / (double)count : 0.0;
-        const double rho = 1.0 + drho;
-        const DevBody &bd = B.bodies[old - 1];
-        double r[3], u[3];
-        int d[3];
-        lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
-        wall_velocity(bd, r, u);
-        const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        for (int a = 0; a < 19; ++a) {
-            const double eu = ex(a) * u[0] + ey(a) * u[1] + ez(a) * u[2];
-            const double v = wgt(a) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-            Storage<S>::store((S *)popc, (size_t)a * stride + c, (typename Storage<S>::C)v, B.scale);
+            wall_velocity(bd, r, u);
+            const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            if (lane < 19) {
+                const int a = lane;
+                const double eu = ex(a) * u[0] + ey(a) * u[1] + ez(a) * u[2];
+                const double v = wgt(a) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+                Storage<S>::store((S *)popc, (size_t)a * stride + c, (typename Storage<S>::C)v, B.scale);
+            }
         }
     }
-    __threadfence_block();
-    __syncthreads();
-    // pass 3: near-body marks and boundary links, in cell order
-    int running = 0;
-    for (int base = 0; base < ncell; base += kCoupleThreads) {
+}
+
+// pass 3: near-body marks and boundary links of the slice, in cell order,
+// numbered from `first`; needs pass 1 done on the neighbours.  With
+// write = false only counts.  Returns the number of links in the slice.
+__device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int first,
+                         bool write) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
+    int running = first;
+    for (int base = t0; base < t1; base += kCoupleThreads) {
         const int t = base + (int)threadIdx.x;
         int c = -1, cnt = 0;
         unsigned mask = 0;
         unsigned char owners[19];
-        if (t < ncell) {
-            const int i = sh.lo[0] + t % bx, j = sh.lo[1] + (t / bx) % by, k = sh.lo[2] + t / (bx * by);
+        if (t < t1) {
+            int i, j, k;
+            map_cell(m, t, i, j, k);
             c = i + nx * (j + ny * k);
             if (c < 0 || c >= B.N) c = -1;
             if (c >= 0 && (B.flags[c] & kOwnerMask) == 0) {
+                // all 18 neighbour flags are loaded before any is used, so
+                // that their latencies overlap (a missing neighbour reads the
+                // cell itself and is masked out)
+                int nidx[19];
+                unsigned ok = 0;
+#pragma unroll
                 for (int a = 1; a < 19; ++a) {
                     int ti, tj, tk;
-                    owners[a] = 0;
-                    if (!neighbour_rt(a, i, j, k, nx, ny, nz, per, ti, tj, tk)) continue;
-                    const int o = B.flags[ti + nx * (tj + ny * tk)] & kOwnerMask;
+                    const bool in = neighbour_rt(a, i, j, k, nx, ny, nz, per, ti, tj, tk);
+                    nidx[a] = in ? ti + nx * (tj + ny * tk) : c;
+                    ok |= in ? 1u << a : 0u;
+                }
+                uint8_t nf[19];
+#pragma unroll
+                for (int a = 1; a < 19; ++a) nf[a] = B.flags[nidx[a]];
+#pragma unroll
+                for (int a = 1; a < 19; ++a) {
+                    const int o = (ok >> a) & 1u ? nf[a] & kOwnerMask : 0;
+                    owners[a] = (unsigned char)o;
                     if (o) {
                         mask |= 1u << a;
-                        owners[a] = (unsigned char)o;
                         ++cnt;
                     }
                 }
@@ -543,7 +646,7 @@ __device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, doubl
         }
         int tot;
         const int off = running + block_scan(cnt, &tot, sh);
-        if (c >= 0 && (B.flags[c] & kOwnerMask) == 0) {
+        if (write && c >= 0 && (B.flags[c] & kOwnerMask) == 0) {
             B.flags[c] = cnt ? kNearBit : 0;
             if (cnt) {
                 B.link_base[c] = off;
@@ -561,10 +664,120 @@ __device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, doubl
         }
         running += tot;
     }
-    if (threadIdx.x == 0) {
-        Bg.link_count = running;
-        if (running > B.link_cap) Bg.status = -6;
+    return running - first;
+}
+
+// Record the positions and orientations the mapping used (the remap skip
+// measures motion from them).
+__device__ void map_record(const BoxDesc &B, const CoupleShared &sh, double *qmaps) {
+    const int b = threadIdx.x;
+    if (b < B.nb) {
+        for (int q = 0; q < 3; ++q) B.bodies[b].Xmap[q] = sh.body[b].anchor[q] + sh.body[b].D[q];
+        for (int q = 0; q < 4; ++q) qmaps[4 * b + q] = sh.body[b].q[q];
     }
+}
+
+// The whole mapping by one workgroup.
+template <typename S>
+__device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, double *qmaps, double *margins) {
+    const MapBox m = map_box(sh);
+    map_owners(B, sh, m, 0, m.ncell);
+    for (int b = 0; b < B.nb; ++b) {
+        const double mm = block_min(map_margin(B, sh.body[b], m, 0, m.ncell), sh);
+        if (threadIdx.x == 0) margins[b] = mm;
+    }
+    map_record(B, sh, qmaps);
+    __threadfence_block();
+    __syncthreads();
+    map_refill<S>(B, sh, m, 0, m.ncell, sh.cur);
+    __threadfence_block();
+    __syncthreads();
+    const int total = map_links(B, sh, m, 0, m.ncell, 0, true);
+    if (threadIdx.x == 0) {
+        Bg.link_count = total;
+        if (total > B.link_cap) Bg.status = -6;
+    }
+}
+
+// Barrier over the kRedBlocks workgroups of one box.  A cooperative launch
+// is only made when every workgroup of it can be resident at once; the wait
+// is bounded all the same, so that a workgroup never waits for ever: on
+// time-out the box is marked failed (status -7) and the kernel drains.
+// Waiting workgroups poll with plain device-coherent loads and take one
+// acquire fence at the end: an acquire on every poll would invalidate their
+// L2 over and over, slowing the workgroup that everyone waits for.
+__device__ bool box_barrier(CoupleCtl *ctl, CoupleShared &sh, BoxDesc &Bg) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this thread's stores visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned a = __hip_atomic_fetch_add(&ctl->arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        if (a == kRedBlocks - 1) {
+            __hip_atomic_store(&ctl->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    __hip_atomic_store(&Bg.status, -7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        sh.sync_ok = ok;
+    }
+    __syncthreads();
+    return sh.sync_ok != 0;
+}
+
+// The whole mapping by the kRedBlocks workgroups of a box, r being this
+// one's rank: one contiguous slice of the cell range each, with a barrier
+// where a pass needs its neighbours' results.  The link count of every
+// slice goes through the control block, so that each slice numbers its
+// links from the sum of the counts before it: the list comes out in the same
+// cell order, and every result bit for bit the same, as with one workgroup.
+template <typename S>
+__device__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, CoupleCtl *ctl, int r, double *qmaps,
+                           double *margins) {
+    const MapBox m = map_box(sh);
+    const int chunk = (m.ncell + kRedBlocks - 1) / kRedBlocks;
+    const int t0 = min(r * chunk, m.ncell), t1 = min(t0 + chunk, m.ncell);
+    map_owners(B, sh, m, t0, t1);
+    for (int b = 0; b < B.nb; ++b) {
+        // non-negative doubles order like their bit patterns
+        double mm = map_margin(B, sh.body[b], m, t0, t1);
+        for (int o = 32; o > 0; o >>= 1) mm = fmin(mm, __shfl_xor(mm, o, 64));
+        if ((threadIdx.x & 63) == 0)
+            atomicMin(&ctl->margin[b], (unsigned long long)__double_as_longlong(mm));
+    }
+    if (!box_barrier(ctl, sh, Bg)) return;
+    if (r == 0) map_record(B, sh, qmaps);
+    if (r == 0 && (int)threadIdx.x < B.nb)
+        margins[threadIdx.x] = __longlong_as_double(
+            (long long)__hip_atomic_load(&ctl->margin[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    map_refill<S>(B, sh, m, t0, t1, sh.cur);
+    const int mine = map_links(B, sh, m, t0, t1, 0, false);
+    if (threadIdx.x == 0) __hip_atomic_store(&ctl->counts[r], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!box_barrier(ctl, sh, Bg)) return;
+    if (threadIdx.x == 0) {
+        int first = 0, total = 0;
+        for (int q = 0; q < kRedBlocks; ++q) {
+            const int n = __hip_atomic_load(&ctl->counts[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (q < r) first += n;
+            total += n;
+        }
+        sh.first = first;
+        if (r == kRedBlocks - 1) {
+            Bg.link_count = total;
+            if (total > B.link_cap) Bg.status = -6;
+        }
+    }
+    __syncthreads();
+    map_links(B, sh, m, t0, t1, sh.first, true);
 }
 
 
@@ -617,7 +830,7 @@ __device__ void stage_out(const BoxDesc &B, CoupleShared &sh) {
 template <typename S>
 __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, const int *active,
                                                                 double *qmaps, double *margins,
-                                                                int mode, int force_map) {
+                                                                int mode, int force_map, int coop) {
     __shared__ CoupleShared sh;
     const int bi = active[blockIdx.x / kRedBlocks];
     const int r = blockIdx.x % kRedBlocks;
@@ -625,32 +838,77 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     // snapshot of the descriptor, taken before this kernel stores into it, so
     // that no later read has to wait for those stores
     const BoxDesc B = Bg;
+    CoupleCtl *ctl = (CoupleCtl *)B.ctl;
     double *qm = qmaps + (size_t)bi * 4 * kMaxBodies;
     double *mg = margins + (size_t)bi * kMaxBodies;
+    // the box's workgroups stay to share a remap only if the last step found
+    // that one may come (a remap it did not foresee is done by the finishing
+    // workgroup alone)
+    const int hint = __hip_atomic_load(&ctl->share, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool share = coop && (mode == kModeMapOnly || force_map || hint != 0);
+    bool lead;
     if (mode == kModeStep) {
         reduce_links(B, r, sh);
         // the last workgroup of this box to finish goes on
         __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) sh.last = atomicAdd(B.counter, 1) == kRedBlocks - 1;
+        if (threadIdx.x == 0) sh.last = atomicAdd(&ctl->counter, 1) == kRedBlocks - 1;
         __syncthreads();
-        if (!sh.last) return;
-        __threadfence();
-        if (threadIdx.x == 0) {
-            *B.counter = 0;
-            sh.cur = B.cur;
+        lead = sh.last != 0;
+        if (lead) {
+            __threadfence();
+            if (threadIdx.x == 0) {
+                ctl->counter = 0;
+                sh.cur = B.cur;
+            }
+            stage_in(B, sh, qm, mg);
+            finish_forces(B, sh);
+            rigid_step(B, Bg, sh);
         }
-        stage_in(B, sh, qm, mg);
-        finish_forces(B, sh);
-        rigid_step(B, Bg, sh);
     } else {
-        if (r != 0) return;
-        if (threadIdx.x == 0) sh.cur = B.cur;
-        stage_in(B, sh, qm, mg);
+        lead = r == 0;
+        if (lead) {
+            if (threadIdx.x == 0) sh.cur = B.cur;
+            stage_in(B, sh, qm, mg);
+        }
     }
-    if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
-    stage_out(B, sh);
-    if (sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
+    if (!share && !lead) return;
+    if (lead) {
+        if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
+        stage_out(B, sh);
+        // every other workgroup has read this step's hint before the leader
+        // was known, so the next step's may be stored now
+        if (threadIdx.x == 0) ctl->share = sh.share_next;
+        if (!share) {
+            if (sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
+            return;
+        }
+        // hand the decision to the box's other workgroups
+        if (threadIdx.x == 0) {
+            ctl->map_req = sh.map_req;
+            ctl->cur = sh.cur;
+            for (int q = 0; q < 3; ++q) {
+                ctl->lo[q] = sh.lo[q];
+                ctl->hi[q] = sh.hi[q];
+            }
+        }
+        if (sh.map_req && (int)threadIdx.x < B.nb)
+            ctl->margin[threadIdx.x] = (unsigned long long)__double_as_longlong(1e300);
+    }
+    if (!box_barrier(ctl, sh, Bg)) return;
+    if (threadIdx.x == 0) {
+        sh.map_req = __hip_atomic_load(&ctl->map_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.cur = __hip_atomic_load(&ctl->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = 0; q < 3; ++q) {
+            sh.lo[q] = __hip_atomic_load(&ctl->lo[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh.hi[q] = __hip_atomic_load(&ctl->hi[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    if (!sh.map_req) return;
+    if (!lead) copy_words(sh.body, B.bodies, (int)sizeof(DevBody) * B.nb);   // the bodies' new states
+    __syncthreads();
+    remap_coop<S>(B, Bg, sh, ctl, r, qm, mg);
 }
 
 }  // namespace lbm

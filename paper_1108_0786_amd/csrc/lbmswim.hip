@@ -43,7 +43,7 @@ struct HostBox {
     int *link_base = nullptr;
     uint8_t *old_owner = nullptr;
     void *partials = nullptr;
-    int *counter = nullptr;
+    CoupleCtl *ctl = nullptr;
     int link_cap = 0;
     bool mapped = false;
 };
@@ -63,6 +63,8 @@ struct lbm_ctx {
     std::vector<int> active_host;
     bool work_dirty = true;
     bool force_map = false;
+    bool coop_remap = true;        // share the mapping among a box's coupling workgroups
+    int coop_blocks = 0;           // coupling workgroups that are surely resident at once
     bool poisoned = false;
     bool timing = false;
     int block = kDefaultBlock;
@@ -161,7 +163,7 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.traj = h.p.traj;
     d.traj_cap = h.p.traj ? h.p.traj_cap : 0;
     d.partials = h.partials;
-    d.counter = h.counter;
+    d.ctl = h.ctl;
     return d;
 }
 
@@ -172,6 +174,16 @@ int upload_desc(lbm_ctx *c, int b) {
     const size_t static_bytes = offsetof(BoxDesc, step);
     HIP_TRY(c, hipMemcpyAsync(c->d_boxes + b, &d, static_bytes, hipMemcpyHostToDevice, c->stream));
     return LBM_OK;
+}
+
+template <typename F>
+int dispatch_storage(int storage, F &&f) {
+    switch (storage) {
+        case LBM_F64: return f((double *)nullptr);
+        case LBM_F32: return f((float *)nullptr);
+        case LBM_F16S: return f((_Float16 *)nullptr);
+        default: return f((bf16_t *)nullptr);
+    }
 }
 
 int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
@@ -204,7 +216,7 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
         if (hipMalloc(&h.link_base, sizeof(int) * h.N) != hipSuccess ||
             hipMalloc(&h.old_owner, h.N) != hipSuccess ||
             hipMalloc(&h.partials, sizeof(Partial) * kRedBlocks * kMaxBodies) != hipSuccess ||
-            hipMalloc(&h.counter, sizeof(int)) != hipSuccess) {
+            hipMalloc(&h.ctl, sizeof(CoupleCtl)) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "out of device memory for per-cell scratch");
         }
@@ -212,7 +224,7 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
             hipMemsetAsync(h.old_owner, 0, h.N, c->stream) != hipSuccess ||
             hipMemsetAsync(h.link_base, 0, sizeof(int) * h.N, c->stream) != hipSuccess ||
             hipMemsetAsync(h.partials, 0, sizeof(Partial) * kRedBlocks * kMaxBodies, c->stream) != hipSuccess ||
-            hipMemsetAsync(h.counter, 0, sizeof(int), c->stream) != hipSuccess) {
+            hipMemsetAsync(h.ctl, 0, sizeof(CoupleCtl), c->stream) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "clearing flags failed");
         }
@@ -224,6 +236,19 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     HIP_TRY(c, hipMalloc(&c->d_margins, sizeof(double) * kMaxBodies * nbox));
     HIP_TRY(c, hipMemsetAsync(c->d_margins, 0, sizeof(double) * kMaxBodies * nbox, c->stream));
     HIP_TRY(c, hipMalloc(&c->d_active, sizeof(int) * nbox));
+    {
+        // how many coupling workgroups the device holds at once
+        int dev = 0, ncu = 0, per_cu = 0;
+        HIP_TRY(c, hipGetDevice(&dev));
+        HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int rc0 = dispatch_storage(c->storage, [&](auto *tag) -> int {
+            using S = std::remove_pointer_t<decltype(tag)>;
+            HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, couple_kernel<S>, kCoupleThreads, 0));
+            return LBM_OK;
+        });
+        if (rc0 != LBM_OK) return rc0;
+        c->coop_blocks = per_cu * ncu;
+    }
     for (int b = 0; b < nbox; ++b) {
         int rc = upload_desc(c, b);
         if (rc != LBM_OK) return rc;
@@ -343,23 +368,15 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
     return LBM_OK;
 }
 
-template <typename F>
-int dispatch_storage(int storage, F &&f) {
-    switch (storage) {
-        case LBM_F64: return f((double *)nullptr);
-        case LBM_F32: return f((float *)nullptr);
-        case LBM_F16S: return f((_Float16 *)nullptr);
-        default: return f((bf16_t *)nullptr);
-    }
-}
-
 // Coupling kernel: kRedBlocks workgroups per active box.
 int launch_couple(lbm_ctx *c, const int *active_dev, int nactive, int mode) {
     if (nactive == 0) return LBM_OK;
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
+        // cooperative only if every workgroup of the launch is resident at once
+        const int coop = c->coop_remap && nactive * kRedBlocks <= c->coop_blocks ? 1 : 0;
         hipLaunchKernelGGL(couple_kernel<S>, dim3(nactive * kRedBlocks), dim3(kCoupleThreads), 0, c->stream,
-                           c->d_boxes, active_dev, c->d_qmaps, c->d_margins, mode, c->force_map ? 1 : 0);
+                           c->d_boxes, active_dev, c->d_qmaps, c->d_margins, mode, c->force_map ? 1 : 0, coop);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("couple launch: ") + hipGetErrorString(e));
         return LBM_OK;
@@ -1064,6 +1081,8 @@ int lbm_status(lbm_ctx *c) {
             return fail(c, LBM_E_UNSTABLE, "box " + std::to_string(b) + ": non-finite body force or state");
         if (d[b].status == LBM_E_CAPACITY)
             return fail(c, LBM_E_CAPACITY, "box " + std::to_string(b) + ": link list overflow");
+        if (d[b].status == LBM_E_SYNC)
+            return fail(c, LBM_E_SYNC, "box " + std::to_string(b) + ": coupling workgroups timed out at a barrier");
     }
     return LBM_OK;
 }
@@ -1092,6 +1111,10 @@ int lbm_tune(lbm_ctx *c, int32_t key, int64_t value) {
         case LBM_TUNE_FULL_REMAP:
             if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "full remap is 0 or 1");
             c->force_map = value != 0;
+            break;
+        case LBM_TUNE_COOP_REMAP:
+            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "cooperative remap is 0 or 1");
+            c->coop_remap = value != 0;
             break;
         default:
             return fail(c, LBM_E_ARG, "unknown tuning key");
@@ -1165,7 +1188,7 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipFree(h.link_base);
         (void)hipFree(h.old_owner);
         (void)hipFree(h.partials);
-        (void)hipFree(h.counter);
+        (void)hipFree(h.ctl);
     }
     (void)hipFree(c->d_boxes);
     (void)hipFree(c->d_qmaps);
