@@ -1,23 +1,31 @@
-"""Swimmers of the Sec. 5.1 design study, run on the GPU at the paper's size
-(200x100x100, tau 2/3, five driving periods of 28116 steps, FP32 storage,
-two-step force mean): the three-sphere designs (a) and (q) and the
-all-capsule designs (f), (k) and (p).  Post-processed with the Eq. arms fit
-and the GA formulas (Eqs. K, V_GA; a capsule counts as a sphere of
-diameter 12, as in Sec. 5.3.2) and compared with what the paper reports
-(Tables tab:spheres, tab:sphere_params, tab:caps_family1-3 and the
-appendix parameter tables).
+"""The Sec. 5.1 design study on the GPU at the paper's size: all seventeen
+swimmers of Table tab:designs, run side by side as one batch of seventeen
+200x100x100 channels (tau 2/3, five driving periods of 28116 steps, FP32
+storage, two-step force mean).  Post-processed with the Eq. arms fit, the GA
+formulas (Eqs. K, V_GA; a capsule counts as a sphere of diameter 12, Sec.
+5.3.2), the per-body Reynolds numbers of Eq. ReBody and the efficiency of
+Eq. eff, and compared with what the paper reports (Tables tab:designs,
+tab:spheres, tab:sphere_params, tab:caps_family1-3 and the appendix
+parameter tables).
 
 Asserted, because they follow from the physics and the paper's own findings
 rather than from details of its code:
-  * the run stays smooth (no step-to-step oscillation of the bodies);
+  * every run stays smooth (no step-to-step oscillation of the bodies);
   * the mean arm lengths give the printed GA factors K;
   * the simulated swimming velocity agrees with the GA prediction from the
     fitted arm oscillations as well as the paper's does (its printed error
     bound for the design), with 5 points of slack;
-  * the smaller spheres swim faster than the larger ones ((a) vs (q), Sec.
-    5.3.1) and the long swimmer of perpendicular capsules (k) is the slowest
-    of (f), (k), (p).
-Reported only: u_swim and the arm amplitudes against the printed values."""
+  * the sphere swimmer (a) is the fastest, (q) with the large spheres swims
+    at less than half its speed (Sec. 5.3.1), and within each capsule family
+    the swimmers rank as in the paper's table of that family, corresponding
+    designs taking the same place in every family (Sec. 5.3.2);
+  * an arm next to a capsule oscillates less: of the two designs of a family
+    with one capsule at an end, the one with the capsule on the left has the
+    smaller left arm amplitude d1 and the larger right one d2 (the reading
+    that places the capsule in designs (b)/(d), (g)/(i), (l)/(n)).
+Reported only: u_swim, the arm amplitudes, Re per body and the efficiency,
+against the printed values."""
+import dataclasses
 import json
 import math
 import os
@@ -27,64 +35,90 @@ import pytest
 
 import workloads as W
 from oracle import observables as ob
+from oracle.rigid import driving_forces
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
-SPHERES = ("a", "q")
-_results = {}
+DESIGNS = list("abcdefghijklmnopq")
+FAMILIES = {"parallel": "bcdef", "perpendicular, long": "ghijk", "perpendicular, short": "lmnop"}
+NU = 1.0 / 18.0
 
 
 def _printed(design):
     """Printed u_swim, u_GA error bound, and arm parameters of a design."""
-    if design in SPHERES:
+    if design in "aq":
         sw = GOLD["spheres"][design]
         return sw["u_swim"], sw["error_pct_below"], GOLD["sphere_params"][design]
     sw = GOLD["capsule_swim"][design]
     return sw["u_swim"], sw["error_pct_below"], GOLD["capsule_params"][design]
 
 
-def _run(design):
-    from paper_1108_0786_amd.sim import Sim
-    case = W.paper_design(design, "f32") if design in SPHERES else W.paper_capsule_design(design, "f32")
-    T = int(case.drives[0].period)
-    n = 5 * T
-    print(f"[gpu] paper scale {case.name}: {n} steps FP32", flush=True)
-    sim = Sim(case, storage="f32", traj_cap=n)
-    for p in range(5):
-        sim.step(T)
-        sim.status()
-        print(f"[gpu] paper scale {design}: period {p + 1} done", flush=True)
-    tr = sim.trajectory()
-    sim.close()
+def _length_along_x(body):
+    along = body.shape == W.CAPSULE and body.quat[0] == 1.0
+    return 2.0 * (body.radius + (body.half_len if along else 0.0))
+
+
+def _analyse(design, case, tr, T):
+    """Observables of one swimmer from the last full period of its run."""
+    tr = tr[np.argsort(tr[:, 0, 15])]
     steps = tr[:, 0, 15].astype(np.int64)
-    order = np.argsort(steps)
-    tr = tr[order]
-    assert np.array_equal(tr[:, 0, 15].astype(np.int64), np.arange(n))
+    assert np.array_equal(steps, np.arange(4 * T - 1, 5 * T)), "trajectory ring misses steps"
     X = np.array([b.anchor[0] for b in case.bodies])[None, :] + tr[:, :, 0]
     V = tr[:, :, 3]
     t = np.arange(4 * T, 5 * T)
     om = 2.0 * math.pi / T
-    lb1, d1, p1 = ob.fit_arm(t, X[4 * T:5 * T, 0] - X[4 * T:5 * T, 1], om)
-    lb2, d2, p2 = ob.fit_arm(t, X[4 * T:5 * T, 2] - X[4 * T:5 * T, 0], om)
-    r = case.bodies[0].radius if design in SPHERES else 6.0
-    K = ob.ga_factor(r, r, r, lb1, lb2)
-    out = dict(u_swim=(X[5 * T - 1, 0] - X[4 * T - 1, 0]) / T, d1=d1, d2=d2, sin_dphi=math.sin(p1 - p2), K=K,
-               u_ga=ob.ga_velocity(K, d1, d2, om, p1 - p2),
-               alternating=np.abs(V[1:-1] - 0.5 * (V[:-2] + V[2:])).max(), vmax=np.abs(V).max())
-    u_print, err, par = _printed(design)
-    print(f"[gpu] paper scale ({design}): u_swim {out['u_swim']:.4e} (printed {u_print}e-6), "
-          f"d1 {d1:.3f} (printed {par['d1']}), d2 {d2:.3f} (printed {par['d2']}), "
-          f"sin dphi {out['sin_dphi']:.3f} (printed {par['sin_dphi']}), K {K:.5f} (printed {par['K']}), "
-          f"u_swim/u_GA {out['u_swim'] / out['u_ga']:.3f} (printed error < {err}%), max |V| {out['vmax']:.2e}, "
-          f"alternating part {out['alternating']:.1e}", flush=True)
+    mid, left, right = 0, 1, 2
+    lb1, d1, p1 = ob.fit_arm(t, X[1:, mid] - X[1:, left], om)
+    lb2, d2, p2 = ob.fit_arm(t, X[1:, right] - X[1:, mid], om)
+    reff = [6.0 if b.shape == W.CAPSULE else b.radius for b in case.bodies]
+    K = ob.ga_factor(reff[left], reff[mid], reff[right], lb1, lb2)
+    u_swim = (X[-1, mid] - X[0, mid]) / T
+    # Eq. eff: period-averaged driving power over the last full period; the
+    # record of step n holds the velocity that step n's forces produced
+    drive = [dataclasses.asdict(d) for d in case.drives]
+    power = np.mean([sum(f[0] * V[1 + s, b] for b, f in enumerate(driving_forces(drive, n, len(case.bodies))))
+                     for s, n in enumerate(t)])
+    eff = ob.lighthill_efficiency(NU, sum(reff), u_swim, power)
+    re = {f"re_B{k}": ob.reynolds(np.abs(V[1:, b]).max(), _length_along_x(case.bodies[b]), NU)
+          for k, b in ((2, left), (1, mid), (3, right))}
+    return dict(u_swim=u_swim, d1=d1, d2=d2, sin_dphi=math.sin(p1 - p2), K=K,
+                u_ga=ob.ga_velocity(K, d1, d2, om, p1 - p2), efficiency=eff, **re,
+                alternating=np.abs(V[1:-1] - 0.5 * (V[:-2] + V[2:])).max(), vmax=np.abs(V).max())
+
+
+@pytest.fixture(scope="module")
+def study():
+    from paper_1108_0786_amd.sim import BatchSim
+    cases = [W.paper_design(d, "f32") for d in DESIGNS]
+    T = W.PAPER_SI["period"]
+    print(f"[gpu] design study: {len(cases)} swimmers, 200x100x100 each, {5 * T} steps FP32", flush=True)
+    sim = BatchSim(cases, storage="f32", traj_cap=T + 1)
+    for p in range(5):
+        sim.step(T)
+        sim.status()
+        print(f"[gpu] design study: period {p + 1} done", flush=True)
+    out = {d: _analyse(d, c, sim.trajectory(i), T) for i, (d, c) in enumerate(zip(DESIGNS, cases))}
+    sim.close()
+    for d in DESIGNS:
+        r = out[d]
+        u_print, err, par = _printed(d)
+        row = GOLD["designs"][d]
+        print(f"[gpu] ({d}) u_swim {r['u_swim'] * 1e6:.3f}e-6 (printed {u_print}), "
+              f"d1 {r['d1']:.2f} ({par['d1']}), d2 {r['d2']:.2f} ({par['d2']}), "
+              f"sin dphi {r['sin_dphi']:.2f} ({par['sin_dphi']}), K {r['K']:.5f} ({par['K']}), "
+              f"u_swim/u_GA {r['u_swim'] / r['u_ga']:.3f} (error < {err}%), "
+              f"Re B2/B1/B3 {r['re_B2']:.3f}/{r['re_B1']:.3f}/{r['re_B3']:.3f} "
+              f"({row['re_B2']}/{row['re_B1']}/{row['re_B3']}), "
+              f"efficiency {r['efficiency'] * 1e4:.2f}e-4 ({GOLD['efficiency'][d]}), "
+              f"alternating/max |V| {r['alternating'] / r['vmax']:.1e}", flush=True)
     return out
 
 
-@pytest.mark.parametrize("design", ["a", "q", "f", "k", "p"])
-def test_design_study_swimmer(design):
-    res = _results[design] = _run(design)
+@pytest.mark.parametrize("design", DESIGNS)
+def test_design_study_swimmer(study, design):
+    res = study[design]
     _, err, par = _printed(design)
     assert np.isfinite(res["u_swim"])
     # the remap impulses leave a step-to-step part of about 1e-3 of the peak
@@ -92,7 +126,19 @@ def test_design_study_swimmer(design):
     assert res["alternating"] < 1e-2 * res["vmax"]
     assert abs(res["K"] - par["K"]) < 0.00006
     assert abs(res["u_swim"] / res["u_ga"] - 1.0) < err / 100.0 + 0.05
-    if design == "q" and "a" in _results:
-        assert _results["a"]["u_swim"] > 2.0 * res["u_swim"]
-    if design == "p" and "f" in _results and "k" in _results:
-        assert _results["k"]["u_swim"] < min(_results["f"]["u_swim"], res["u_swim"])
+
+
+def test_design_study_orderings(study):
+    u = {d: study[d]["u_swim"] for d in DESIGNS}
+    assert u["a"] == max(u.values())
+    assert u["a"] > 2.0 * u["q"]
+    printed = GOLD["capsule_swim"]
+    for name, family in FAMILIES.items():
+        assert sorted(family, key=lambda d: u[d]) == sorted(family, key=lambda d: printed[d]["u_swim"]), name
+    assert u["k"] < min(u["f"], u["p"])
+
+
+@pytest.mark.parametrize("left,right", [("b", "d"), ("g", "i"), ("l", "n")])
+def test_capsule_side_follows_the_arm_amplitudes(study, left, right):
+    assert study[left]["d1"] < study[right]["d1"]
+    assert study[left]["d2"] > study[right]["d2"]

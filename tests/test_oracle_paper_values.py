@@ -54,10 +54,11 @@ def test_ga_velocity_reproduces_capsule_tables():
         assert math.isclose(u * 1e6, GOLD["capsule_velocities"][d], rel_tol=0.05), d
 
 
-@pytest.mark.parametrize("design", ["a", "q"])
+@pytest.mark.parametrize("design", list("abcdefghijklmnopq"))
 def test_swimmer_reynolds_number(design):
     # Eq. ReSwimmer: Re = u_swim l_swim / nu with nu = 1/18 in lattice units
-    u = GOLD["spheres"][design]["u_swim"] * 1e-6
+    table = GOLD["spheres"] if design in "aq" else GOLD["capsule_swim"]
+    u = table[design]["u_swim"] * 1e-6
     l = GOLD["designs"][design]["total_length"]
     re = ob.reynolds(u, l, 1.0 / 18.0)
     assert math.isclose(re * 1e3, GOLD["designs"][design]["re_swim"], abs_tol=0.01)
@@ -88,3 +89,38 @@ def test_arm_fit_recovers_amplitude_and_phase():
     assert math.isclose(lbar, 16.0, rel_tol=1e-12)
     assert math.isclose(d, 0.37, rel_tol=1e-10)
     assert math.isclose(phi, 0.8, rel_tol=1e-10)
+
+
+def _extent(body, axis):
+    """Half extent of a body along a lattice axis (0 x, 1 y): capsules are
+    either unturned (core along x) or turned by 90 degrees about z (core along y)."""
+    import workloads as W
+    if body.shape != W.CAPSULE:
+        return body.radius
+    along_x = body.quat[0] == 1.0
+    return body.radius + (body.half_len if along_x == (axis == 0) else 0.0)
+
+
+@pytest.mark.parametrize("design", list("abcdefghijklmnopq"))
+def test_design_workloads_match_the_design_table(design):
+    # Table tab:designs prints each swimmer's rest length along its axis and
+    # its width; Sec. 5.1 gives the body sizes and the spring rules, and the
+    # appendix tables the GA factor of each design (capsules counted as
+    # spheres of diameter 12, Sec. 5.3.2)
+    import workloads as W
+    case = W.paper_design(design)
+    mid, left, right = case.bodies
+    length = (right.anchor[0] + _extent(right, 0)) - (left.anchor[0] - _extent(left, 0))
+    width = 2.0 * max(_extent(b, 1) for b in case.bodies)
+    row = GOLD["designs"][design]
+    assert (length, width) == (row["total_length"], row["total_width"])
+    reff = [6.0 if b.shape == W.CAPSULE else b.radius for b in (left, mid, right)]
+    K = ob.ga_factor(*reff, mid.anchor[0] - left.anchor[0], right.anchor[0] - mid.anchor[0])
+    printed = (GOLD["sphere_params"] if design in "aq" else GOLD["capsule_params"])[design]["K"]
+    assert abs(K - printed) <= 0.00006
+    # springs at rest, equal masses, every body centred in the channel
+    for sp in case.springs:
+        gap = case.bodies[sp.i].anchor[0] - case.bodies[sp.j].anchor[0]
+        assert abs(gap) == sp.rest_len
+    assert len({b.mass for b in case.bodies}) == 1
+    assert mid.anchor == (case.nx / 2, case.ny / 2, case.nz / 2)

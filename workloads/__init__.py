@@ -263,46 +263,64 @@ def paper_units():
             si["amplitude"] * dt * dt / (mu * si["dx"]))
 
 
+# The Sec. 5.1 design table: bodies (left, middle, right), S a sphere and C a
+# capsule, and the capsules' axis: along the swimmer axis (x) or across it
+# (y).  Which body carries the capsule follows from the printed total
+# lengths, GA factors and per-body Reynolds numbers; for the designs with one
+# capsule at an end it follows from the printed arm amplitudes, the arm next
+# to a capsule oscillating less.
+PAPER_DESIGNS = {
+    "a": ("SSS", None), "q": ("SSS", None),
+    "b": ("CSS", "x"), "c": ("SCS", "x"), "d": ("SSC", "x"), "e": ("CSC", "x"), "f": ("CCC", "x"),
+    "g": ("CSS", "y"), "h": ("SCS", "y"), "i": ("SSC", "y"), "j": ("CSC", "y"), "k": ("CCC", "y"),
+    "l": ("CSS", "y"), "m": ("SCS", "y"), "n": ("SSC", "y"), "o": ("CSC", "y"), "p": ("CCC", "y"),
+}
+
+
+def paper_rest_gap(design: str, a: str, b: str) -> float:
+    """Surface gap of the spring between bodies of kinds ``a`` and ``b``: 8
+    cells, except in the long perpendicular family (g)-(k), where it is 12
+    between a sphere and a capsule and 16 between two capsules, so that those
+    arms are as long as in the parallel family (b)-(f)."""
+    if design in "ghijk":
+        return 8.0 + 4.0 * ((a == "C") + (b == "C"))
+    return 8.0
+
+
 def paper_design(design: str = "a", storage: str = "f64") -> Case:
-    """The three-sphere swimmers of the Sec. 5.1 design study: (a) radius 4,
-    (q) radius 8, surface gaps of 8 cells, equal masses, tau 2/3, centred in a
-    200x100x100 channel (swimmer axis x, periodic; walls in y and z).  The
-    right force starts a quarter period late and the forces are switched off
+    """A swimmer of the Sec. 5.1 design study, centred in a 200x100x100
+    channel (swimmer axis x, periodic; walls in y and z), tau 2/3.
+
+    Spheres of radius 4 ((q): radius 8), capsules of radius 4 and length 16
+    (cylinder 8); every body has the same mass.  Spring rest lengths are
+    surface gaps (``paper_rest_gap``) plus the bodies' half extents along x.
+    The right force starts a quarter period late; the forces are switched off
     after five periods (left) and a quarter period later (right and middle);
-    196812 steps in all.  The bodies move with the two-step mean of the
-    hydrodynamic force: at tau = 2/3 the plain explicit coupling lets a
-    period-2 oscillation grow until the swimmer is torn apart."""
-    r = {"a": 4.0, "q": 8.0}[design]
+    196812 steps in all.  Capsules do not rotate.  The bodies move with the
+    two-step mean of the hydrodynamic force: at tau = 2/3 the plain explicit
+    coupling lets a period-2 oscillation grow until the swimmer is torn
+    apart."""
+    kinds, axis = PAPER_DESIGNS[design]
+    r, h = (8.0 if design == "q" else 4.0), 4.0
     m, k, gamma, a = paper_units()
     T = PAPER_SI["period"]
-    l0 = 8.0 + 2.0 * r
-    b, s, d = swimmer((100.0, 50.0, 50.0), r=r, l0=(l0, l0), k=k, gamma=gamma, mass=m,
+
+    def half(kind):
+        return r + h if (kind == "C" and axis == "x") else r
+
+    left, middle, right = kinds
+    l0 = (paper_rest_gap(design, left, middle) + half(left) + half(middle),
+          paper_rest_gap(design, middle, right) + half(middle) + half(right))
+    shapes = tuple(CAPSULE if c == "C" else SPHERE for c in (middle, left, right))
+    b, s, d = swimmer((100.0, 50.0, 50.0), shapes=shapes, r=r, h=h, l0=l0, k=k, gamma=gamma, mass=m,
                       amplitude=a, period=float(T), phase_lag=math.pi / 2, gate_lagged=True,
-                      off_left=5 * T, off_right=5 * T + T // 4)
-    return Case(f"paper_{design}_200x100x100", 200, 100, 100, 2.0 / 3.0, bodies=b, springs=s, drives=[d],
-                steps=196812, storage=storage, force_average=True)
-
-
-def paper_capsule_design(design: str = "f", storage: str = "f64") -> Case:
-    """The all-capsule swimmers of the Sec. 5.1 design study, in the channel of
-    ``paper_design``: (f) three capsules along the swimmer axis, surface gaps
-    8; (k) three capsules across it (axis along y), gaps 16; (p) the same
-    with gaps 8.  Capsules of radius 4 and length 16 (cylinder 8) with the
-    spheres' mass, rotation locked, moved with the two-step force mean."""
-    r, h = 4.0, 4.0
-    m, k, gamma, a = paper_units()
-    T = PAPER_SI["period"]
-    across = design in ("k", "p")
-    gap = {"f": 8.0, "k": 16.0, "p": 8.0}[design]
-    l0 = gap + 2.0 * (r if across else r + h)
-    b, s, d = swimmer((100.0, 50.0, 50.0), shapes=(CAPSULE, CAPSULE, CAPSULE), r=r, h=h, l0=(l0, l0), k=k,
-                      gamma=gamma, mass=m, amplitude=a, period=float(T), phase_lag=math.pi / 2, gate_lagged=True,
                       off_left=5 * T, off_right=5 * T + T // 4)
     c45 = math.sqrt(0.5)
     for body in b:
-        body.kinematic = 2
-        if across:
-            body.quat = (c45, 0.0, 0.0, c45)   # body x axis turned onto y
+        if body.shape == CAPSULE:
+            body.kinematic = 2
+            if axis == "y":
+                body.quat = (c45, 0.0, 0.0, c45)   # body x axis turned onto y
     return Case(f"paper_{design}_200x100x100", 200, 100, 100, 2.0 / 3.0, bodies=b, springs=s, drives=[d],
                 steps=196812, storage=storage, force_average=True)
 
