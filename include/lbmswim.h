@@ -209,6 +209,28 @@ int lbm_export_cells(lbm_ctx *ctx, int32_t box, const int32_t *cells, int64_t n,
  * (19*N doubles of dF), converting to the storage type. */
 int lbm_import_populations(lbm_ctx *ctx, int32_t box, const double *src);
 
+/* Time-averaged flow field (Sec. 6, Fig. flowfields13: flow fields averaged
+ * over swimming cycles).  lbm_flow_average_begin(ctx, box, every) with
+ * every >= 1 clears box `box`'s sums and from then on adds, at every step n
+ * with n % every == 0 (n the box's step counter), the fluid velocity
+ * u = sum_alpha e_alpha f_alpha / rho of the pre-collision state of step n
+ * at every cell that is fluid in that step, in double, together with a
+ * per-cell count of the samples.  every = 0 stops sampling and keeps the
+ * sums.  The sums (3N doubles and N ints) are library-owned, allocated on
+ * first use and freed by lbm_destroy.  Steps that sample run a variant of
+ * the sweep that reads and writes 28 more bytes per fluid cell; the plain
+ * sweep is used while no box samples.  Synchronising.  LBM_E_ARG for a bad
+ * box or every < 0; lbm_adjoint returns LBM_E_STATE while a box samples.
+ *
+ * lbm_flow_average_get writes the mean velocity sum / count into the
+ * caller-owned device array `mean` (3*N doubles: x, then y, then z, each
+ * [nz][ny][nx]; zero where the cell was never fluid in a sample) and, if
+ * `count` is not null, the counts into the device array `count` (N int32).
+ * Asynchronous on the context's stream.  LBM_E_STATE if no average was
+ * begun on the box. */
+int lbm_flow_average_begin(lbm_ctx *ctx, int32_t box, int32_t every);
+int lbm_flow_average_get(lbm_ctx *ctx, int32_t box, double *mean, int32_t *count);
+
 /* Steps taken by box `box` so far.  Synchronising. */
 int lbm_step_count(lbm_ctx *ctx, int32_t box, int64_t *steps);
 

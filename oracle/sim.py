@@ -21,6 +21,13 @@ light enough bodies the explicit coupling then amplifies that period-2 mode;
 the two-step mean removes it exactly.  The recorded F and T stay the
 momentum-exchange sums of the step itself.
 
+Time-averaged flow field (Sec. 6, Fig. flowfields13: flow fields averaged
+over five swimming cycles).  A reading, as the paper gives only the figure:
+the average at a cell is the mean of the fluid velocity u = j / rho of
+Sec. 2.1 over the sampled steps in which the cell is fluid.  A step n is
+sampled when n % every == 0; its velocity is that of the pre-collision state
+of step n after its mapping, the state step 2 starts from.
+
 The state is held in deviation form (oracle.lbm).  With ``dtype=complex128``
 the same code runs the complex-step tangent: a parameter given an imaginary
 perturbation i h propagates so that Im(J)/h is dJ/dparameter to rounding
@@ -86,6 +93,7 @@ class OracleSim:
         self.force_average = bool(getattr(case, "force_average", False))
         self.F_prev = [[0.0, 0.0, 0.0] for _ in self.bodies]
         self.T_prev = [[0.0, 0.0, 0.0] for _ in self.bodies]
+        self.flow_every = 0
         self.remap()
 
     # -- step 1 ------------------------------------------------------------
@@ -111,6 +119,11 @@ class OracleSim:
         self.remap()
         dft, rho, u = lbm.collide(self.df, self.tau, self.g)
         self.dft, self.rho = dft, rho
+        if self.flow_every and self.n % self.flow_every == 0:
+            fluid = self.flags == 0
+            for d in range(3):
+                self.flow_sum[d][fluid] = self.flow_sum[d][fluid] + u[d][fluid]
+            self.flow_count[fluid] += 1
         new = lbm.stream_bounce_back(dft, rho, self.flags, self.nbr, self.wall_velocity)
         lc, ld, lb = self.links
         F, T = coupling.momentum_exchange(lc, ld, lb, dft, rho, self.bodies, self.dims,
@@ -147,6 +160,25 @@ class OracleSim:
     def populations(self):
         """Deviations dF with shape (19, nz, ny, nx); zero inside objects."""
         return self.df.reshape(19, self.dims[2], self.dims[1], self.dims[0])
+
+    def flow_average_begin(self, every):
+        """Clear the sums of the time-averaged flow and sample every
+        ``every``-th step from now on (module docstring); 0 stops sampling."""
+        self.flow_every = int(every)
+        if every:
+            self.flow_sum = np.zeros((3, self.N), dtype=self.dtype)
+            self.flow_count = np.zeros(self.N, dtype=np.int64)
+        return self
+
+    def flow_average(self):
+        """(mean fluid velocity with shape (3, nz, ny, nx), zero where a cell
+        was never fluid in a sample; sample counts with shape (nz, ny, nx))."""
+        shape = (self.dims[2], self.dims[1], self.dims[0])
+        mean = np.zeros((3, self.N), dtype=self.dtype)
+        seen = self.flow_count > 0
+        for d in range(3):
+            mean[d][seen] = self.flow_sum[d][seen] / self.flow_count[seen]
+        return mean.reshape((3,) + shape), self.flow_count.reshape(shape)
 
     def centroid_displacement(self):
         """Mean x displacement of the bodies (equal masses): the swimmer's

@@ -17,7 +17,8 @@ TRAJ_DOUBLES = 16
 SYMBOLS = [
     "lbm_init", "lbm_init_batch", "lbm_set_bodies", "lbm_set_bodies_box", "lbm_set_step_limit",
     "lbm_step", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
-    "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations", "lbm_step_count",
+    "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations",
+    "lbm_flow_average_begin", "lbm_flow_average_get", "lbm_step_count",
     "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_copy_kernel", "lbm_struct_sizes", "lbm_last_error",
     "lbm_destroy",
 ]
@@ -86,6 +87,8 @@ def load():
         "lbm_export_populations": ([ctx_p, C.c_int32, C.c_void_p], C.c_int),
         "lbm_import_populations": ([ctx_p, C.c_int32, C.c_void_p], C.c_int),
         "lbm_export_cells": ([ctx_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+        "lbm_flow_average_begin": ([ctx_p, C.c_int32, C.c_int32], C.c_int),
+        "lbm_flow_average_get": ([ctx_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
         "lbm_step_count": ([ctx_p, C.c_int32, P(C.c_int64)], C.c_int),
         "lbm_status": ([ctx_p], C.c_int),
         "lbm_adjoint": ([ctx_p, C.c_int64, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)], C.c_int),

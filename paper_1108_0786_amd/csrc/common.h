@@ -178,6 +178,10 @@ struct BoxDesc {
     long long traj_cap;
     void *partials;            // momentum-exchange partial sums, one slice per reduction workgroup
     void *ctl;                 // control words of the coupling kernel (counter, barrier, remap slices)
+    double *flow_sum;          // 3 arrays of N: summed fluid velocity (x, y, z) for the time average, or null
+    int *flow_count;           // N: samples in which the cell was fluid
+    int flow_every;            // sample the steps n with n % flow_every == 0 (0: none)
+    int pad1;
     // mutable state, advanced on the device
     long long step;
     int cur;                   // index of the buffer holding the current populations

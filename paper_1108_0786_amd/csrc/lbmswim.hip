@@ -44,6 +44,9 @@ struct HostBox {
     uint8_t *old_owner = nullptr;
     void *partials = nullptr;
     CoupleCtl *ctl = nullptr;
+    double *flow_sum = nullptr;  // time-averaged flow: 3N sums and N counts (library-owned)
+    int *flow_count = nullptr;
+    int flow_every = 0;
     int link_cap = 0;
     bool mapped = false;
 };
@@ -64,6 +67,7 @@ struct lbm_ctx {
     bool work_dirty = true;
     bool force_map = false;
     bool coop_remap = true;        // share the mapping among a box's coupling workgroups
+    bool flow_any = false;         // some box samples the time-averaged flow
     int coop_blocks = 0;           // coupling workgroups that are surely resident at once
     bool poisoned = false;
     bool timing = false;
@@ -164,6 +168,9 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.traj_cap = h.p.traj ? h.p.traj_cap : 0;
     d.partials = h.partials;
     d.ctl = h.ctl;
+    d.flow_sum = h.flow_sum;
+    d.flow_count = h.flow_count;
+    d.flow_every = h.flow_every;
     return d;
 }
 
@@ -428,15 +435,22 @@ int rebuild_work(lbm_ctx *c) {
     return LBM_OK;
 }
 
+template <typename S, int BLOCK, bool FLOW>
+int launch_sweep_f(lbm_ctx *c) {
+    if (c->nontemporal)
+        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, true, FLOW>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
+                           c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+    else
+        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, false, FLOW>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
+                           c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+    return LBM_OK;
+}
+
+// The sweep that also samples the time-averaged flow runs only while some
+// box samples it; the plain sweep carries no trace of it.
 template <typename S, int BLOCK>
 int launch_sweep_t(lbm_ctx *c) {
-    if (c->nontemporal)
-        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, true>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream, c->d_boxes,
-                           c->d_work, c->nwork, c->xcd_order);
-    else
-        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, false>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream, c->d_boxes,
-                           c->d_work, c->nwork, c->xcd_order);
-    return LBM_OK;
+    return c->flow_any ? launch_sweep_f<S, BLOCK, true>(c) : launch_sweep_f<S, BLOCK, false>(c);
 }
 
 int launch_sweep(lbm_ctx *c) {
@@ -797,6 +811,7 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
         return fail(c, LBM_E_ARG, "nsteps and checkpoint_every must be >= 1; outputs must be non-null");
     if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
     if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
+    if (c->flow_any) return fail(c, LBM_E_STATE, "stop the flow average before the adjoint (its recomputation would sample)");
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         return adjoint_impl<S>(c, nsteps, checkpoint_every, dJ_ddisp, J, grad);
@@ -1059,6 +1074,52 @@ int lbm_import_populations(lbm_ctx *c, int32_t box, const double *src) {
     });
 }
 
+__global__ void flow_mean_kernel(const double *sum, const int *count, long long n, double *mean, int *cnt_out) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int k = count[c];
+    for (int q = 0; q < 3; ++q) mean[q * n + c] = k ? sum[q * n + c] / (double)k : 0.0;
+    if (cnt_out) cnt_out[c] = k;
+}
+
+int lbm_flow_average_begin(lbm_ctx *c, int32_t box, int32_t every) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (every < 0) return fail(c, LBM_E_ARG, "every must be >= 0");
+    HostBox &h = c->boxes[box];
+    if (every > 0) {
+        if (!h.flow_sum) {
+            if (hipMalloc(&h.flow_sum, sizeof(double) * 3 * (size_t)h.N) != hipSuccess ||
+                hipMalloc(&h.flow_count, sizeof(int) * (size_t)h.N) != hipSuccess)
+                return fail(c, LBM_E_HIP, "out of device memory for the flow average");
+        }
+        HIP_TRY(c, hipMemsetAsync(h.flow_sum, 0, sizeof(double) * 3 * (size_t)h.N, c->stream));
+        HIP_TRY(c, hipMemsetAsync(h.flow_count, 0, sizeof(int) * (size_t)h.N, c->stream));
+    }
+    h.flow_every = every;
+    rc = upload_desc(c, box);
+    if (rc) return rc;
+    c->flow_any = false;
+    for (const HostBox &o : c->boxes) c->flow_any = c->flow_any || o.flow_every > 0;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    return LBM_OK;
+}
+
+int lbm_flow_average_get(lbm_ctx *c, int32_t box, double *mean, int32_t *count) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    const HostBox &h = c->boxes[box];
+    if (!mean) return fail(c, LBM_E_ARG, "null output");
+    if (!h.flow_sum) return fail(c, LBM_E_STATE, "no flow average was begun on this box");
+    const long long n = h.N;
+    hipLaunchKernelGGL(flow_mean_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, h.flow_sum,
+                       h.flow_count, n, mean, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("flow mean launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
 int lbm_step_count(lbm_ctx *c, int32_t box, int64_t *steps) {
     int rc = check_box(c, box);
     if (rc) return rc;
@@ -1189,6 +1250,8 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipFree(h.old_owner);
         (void)hipFree(h.partials);
         (void)hipFree(h.ctl);
+        (void)hipFree(h.flow_sum);
+        (void)hipFree(h.flow_count);
     }
     (void)hipFree(c->d_boxes);
     (void)hipFree(c->d_qmaps);

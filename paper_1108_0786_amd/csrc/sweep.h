@@ -158,6 +158,33 @@ __device__ __forceinline__ C collide(C *f, C omega) {
     return rho;
 }
 
+// Time-averaged flow field (the averaged flow fields of Sec. 6): add the
+// fluid velocity u = j / rho of this cell's pre-collision state to the box's
+// sums, in double, with the moments summed over the directions in ascending
+// order.
+template <typename C>
+__device__ __forceinline__ void flow_sample(const BoxDesc &B, int cell, const C *f) {
+#pragma clang fp contract(off)
+    double drho = (double)f[0];
+    double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        const double v = (double)f[a];
+        drho += v;
+        if (ex(a) == 1) j[0] += v;
+        if (ex(a) == -1) j[0] -= v;
+        if (ey(a) == 1) j[1] += v;
+        if (ey(a) == -1) j[1] -= v;
+        if (ez(a) == 1) j[2] += v;
+        if (ez(a) == -1) j[2] -= v;
+    }
+    const double rho = 1.0 + drho;
+    const size_t n = (size_t)B.N;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) B.flow_sum[q * n + cell] += j[q] / rho;
+    B.flow_count[cell] += 1;
+}
+
 // Interior push: no wall and no body among the neighbours.  off_p / off_m
 // are the linear offsets of the +1 / -1 neighbour along each axis (with the
 // periodic wrap already applied).
@@ -233,7 +260,7 @@ __device__ __forceinline__ int tile_index(int xcd_order) {
     return (w & 7) * per + (w >> 3);
 }
 
-template <typename S, int BLOCK, bool NT>
+template <typename S, int BLOCK, bool NT, bool FLOW>
 __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
                                                       int xcd_order) {
     using St = Storage<S>;
@@ -269,6 +296,9 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
             j = 0;
             ++k;
         }
+    }
+    if constexpr (FLOW) {
+        if (valid && fluid && B.flow_every > 0 && B.step % B.flow_every == 0) flow_sample<C>(B, cell, f);
     }
     const C omega = sizeof(C) == 8 ? (C)B.omega : (C)B.omegaf;
     const C rho = collide<C>(f, omega);

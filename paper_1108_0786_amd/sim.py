@@ -192,6 +192,21 @@ class BatchSim:
         check(self.lib, self.ctx, self.lib.lbm_import_populations(self.ctx, box, C.c_void_p(t.data_ptr())))
         torch.cuda.synchronize(self.device)
 
+    def flow_average_begin(self, every, box=0):
+        """Start (every >= 1, clearing the sums) or stop (every = 0) sampling
+        the time-averaged fluid velocity of a box."""
+        check(self.lib, self.ctx, self.lib.lbm_flow_average_begin(self.ctx, box, int(every)))
+
+    def flow_average(self, box=0):
+        """(mean velocity (3, nz, ny, nx), sample counts (nz, ny, nx)) as numpy."""
+        bx = self.boxes[box]
+        c = bx.case
+        mean = torch.empty(3 * bx.N, dtype=torch.float64, device=self.device)
+        cnt = torch.empty(bx.N, dtype=torch.int32, device=self.device)
+        check(self.lib, self.ctx, self.lib.lbm_flow_average_get(self.ctx, box, C.c_void_p(mean.data_ptr()),
+                                                                C.c_void_p(cnt.data_ptr())))
+        return (mean.cpu().numpy().reshape(3, c.nz, c.ny, c.nx), cnt.cpu().numpy().reshape(c.nz, c.ny, c.nx))
+
     def flags(self, box=0):
         return self.boxes[box].flags.cpu().numpy()
 

@@ -104,3 +104,23 @@ def test_hasimoto_periodic_array_drag():
         F, U, nu, _ = res[L]
         measured = F / (6.0 * math.pi * nu * U)
         assert math.isclose(measured, drag_ratio(Rh, L), rel_tol=0.03)
+
+
+@pytest.mark.parametrize("every", [1, 7])
+def test_time_average_of_steady_couette_flow(every):
+    # the time average of a steady flow is the flow itself: the Couette
+    # profile u = U y / H at every fluid cell, and no samples inside the slab
+    U, H = 1e-3, 10
+    c = 2 ** -0.5
+    slab = W.Body(shape=W.SLAB, radius=1.0, mass=1.0, anchor=(0.0, float(H), 0.0),
+                  quat=(c, 0.0, 0.0, c), vel=(U, 0.0, 0.0), kinematic=True)
+    case = W.Case("couette", 4, H + 2, 4, 0.8, periodic=(True, False, True), bodies=[slab])
+    sim = OracleSim(case).run(3000)
+    start = sim.n
+    sim.flow_average_begin(every).run(50)
+    mean, count = sim.flow_average()
+    samples = len([n for n in range(start, start + 50) if n % every == 0])
+    y = np.arange(H) + 0.5
+    assert np.max(np.abs(mean[0, :, :H, :] - (U * y / H)[None, :, None])) < 1e-12 * U
+    assert np.max(np.abs(mean[1:])) < 1e-15 and not np.any(mean[:, :, H:, :])
+    assert np.all(count[:, :H, :] == samples) and not np.any(count[:, H:, :])

@@ -325,6 +325,30 @@ def paper_design(design: str = "a", storage: str = "f64") -> Case:
                 steps=196812, storage=storage, force_average=True)
 
 
+def paper_flow_channel(swimmers: int = 3, storage: str = "f32") -> Case:
+    """The channel of the averaged flow fields of Sec. 6 (Fig. flowfields13):
+    164x164 cells across, 240 along the swimmer axis (x here, periodic),
+    with the parameters of the design study; one or three swimmers of
+    design (a), driven alike.  The figure alone shows where the three swim;
+    the reading here puts them side by side across the channel, 32 cells
+    apart along y, all centred in z and in x (a plane of mirror symmetry at
+    the middle swimmer, and one through all three)."""
+    one = paper_design("a", storage)
+    bodies, springs, drives = [], [], []
+    offsets = (0.0,) if swimmers == 1 else (-32.0, 0.0, 32.0)
+    if swimmers not in (1, 3):
+        raise ValueError("one or three swimmers")
+    for s_, dy in enumerate(offsets):
+        base = 3 * s_
+        for b in one.bodies:
+            bodies.append(dataclasses.replace(b, anchor=(b.anchor[0] + 20.0, 82.0 + dy, 82.0)))
+        springs += [dataclasses.replace(sp, i=sp.i + base, j=sp.j + base) for sp in one.springs]
+        d = one.drives[0]
+        drives.append(dataclasses.replace(d, left=d.left + base, middle=d.middle + base, right=d.right + base))
+    return Case(f"paper_flow_{swimmers}_240x164x164", 240, 164, 164, one.tau, bodies=bodies, springs=springs,
+                drives=drives, steps=one.steps, storage=storage, force_average=True)
+
+
 def random_small(seed: int, storage: str = "f64") -> Case:
     """A small random box with one to three free, kinematic or rotation-locked
     spheres/capsules,
