@@ -289,6 +289,28 @@ int lbm_tune(lbm_ctx *ctx, int32_t key, int64_t value);
 int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 int lbm_get_timing(lbm_ctx *ctx, double out_ms[2], int64_t out_n[2]);
 
+/* Integrator-only runs: the swimmer in vacuum of Sec. 4 (its Lagrangian
+ * with the spring damping of Eq. damp_i), used there to validate the spring
+ * forces against the analytic model and to trace the amplitude resonances
+ * of Fig. vacuumVal2.  Advances nsys independent systems by nsteps steps of
+ * the rigid-body step that lbm_step uses (driving, Eqs. FB1-FB3; springs,
+ * Eqs. osci_i/j; semi-implicit Euler with dt = 1), with the hydrodynamic
+ * force and torque zero.  Every system has nb bodies, ns springs and nd
+ * drives: system s uses bodies[s*nb .. s*nb+nb-1], springs[s*ns ..] and
+ * drives[s*nd ..] (host arrays, copied; same limits as lbm_set_bodies).
+ * Steps are numbered from 0 for every system.  traj (optional) is a
+ * caller-owned device ring of traj_cap records per system laid out
+ * [nsys][traj_cap][nb][16] like the lbm_params trajectory.  out (optional)
+ * receives the nsys*nb final body states on the host.  Runs on `stream`
+ * (hipStream_t, 0 for the default stream), one workgroup per system, and
+ * synchronises; the few device tables it needs are allocated and freed
+ * inside the call.  LBM_E_ARG for bad counts or indices, non-positive mass,
+ * inertia or period; LBM_E_UNSTABLE if a state became non-finite;
+ * LBM_E_HIP on a runtime error (no context, so no message). */
+int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
+                   const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
+                   int64_t traj_cap, lbm_body *out, void *stream);
+
 /* Measurement aid, not part of the method: copy `bytes` bytes (a multiple
  * of 16) from device memory src to device memory dst with a plain streaming
  * kernel on `stream` (hipStream_t): with blocks_per_cu = 0 one 16-byte vector

@@ -19,7 +19,7 @@ SYMBOLS = [
     "lbm_step", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
     "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations",
     "lbm_flow_average_begin", "lbm_flow_average_get", "lbm_step_count",
-    "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_copy_kernel", "lbm_struct_sizes", "lbm_last_error",
+    "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_vacuum_run", "lbm_copy_kernel", "lbm_struct_sizes", "lbm_last_error",
     "lbm_destroy",
 ]
 
@@ -95,6 +95,8 @@ def load():
         "lbm_tune": ([ctx_p, C.c_int32, C.c_int64], C.c_int),
         "lbm_set_timing": ([ctx_p, C.c_int32], C.c_int),
         "lbm_get_timing": ([ctx_p, P(C.c_double), P(C.c_int64)], C.c_int),
+        "lbm_vacuum_run": ([P(LbmBody), C.c_int32, P(LbmSpring), C.c_int32, P(LbmDrive), C.c_int32, C.c_int32,
+                            C.c_int64, C.c_void_p, C.c_int64, P(LbmBody), C.c_void_p], C.c_int),
         "lbm_copy_kernel": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
         "lbm_struct_sizes": ([P(C.c_int64)], C.c_int),
         "lbm_last_error": ([ctx_p], C.c_char_p),

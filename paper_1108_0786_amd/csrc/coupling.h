@@ -911,4 +911,28 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     remap_coop<S>(B, Bg, sh, ctl, r, qm, mg);
 }
 
+// Integrator-only runs (Sec. 4: the swimmer in vacuum).  One workgroup per
+// system advances it nsteps steps with the rigid-body step of couple_kernel
+// (driving, springs, integration, trajectory record); with no fluid the
+// hydrodynamic force and torque are zero.
+__global__ __launch_bounds__(kCoupleThreads) void vacuum_kernel(BoxDesc *systems, long long nsteps) {
+    __shared__ CoupleShared sh;
+    BoxDesc &Bg = systems[blockIdx.x];
+    BoxDesc B = Bg;
+    copy_words(sh.body, B.bodies, (int)sizeof(DevBody) * B.nb);
+    copy_words(sh.spring, B.springs, (int)sizeof(DevSpring) * B.ns);
+    copy_words(sh.drive, B.drives, (int)sizeof(DevDrive) * B.nd);
+    for (int t = threadIdx.x; t < kMaxBodies * 3; t += kCoupleThreads) {
+        sh.F[t / 3][t % 3] = 0.0;
+        sh.T[t / 3][t % 3] = 0.0;
+    }
+    if (threadIdx.x == 0) sh.cur = B.cur;
+    __syncthreads();
+    for (long long s = 0; s < nsteps; ++s) {
+        rigid_step(B, Bg, sh);
+        B.step += 1;
+    }
+    stage_out(B, sh);
+}
+
 }  // namespace lbm

@@ -818,6 +818,94 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
     });
 }
 
+int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
+                   const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
+                   int64_t traj_cap, lbm_body *out, void *stream) {
+    if (!bodies || nb < 1 || nb > kMaxBodies || ns < 0 || ns > kMaxSprings || nd < 0 || nd > kMaxDrives ||
+        (ns && !springs) || (nd && !drives) || nsys < 1 || nsys > 65535 || nsteps < 0 || traj_cap < 0 ||
+        (traj && traj_cap == 0))
+        return LBM_E_ARG;
+    for (int s = 0; s < nsys; ++s) {
+        for (int b = 0; b < nb; ++b) {
+            const lbm_body &x = bodies[(size_t)s * nb + b];
+            if (x.kinematic < 0 || x.kinematic > 2 || !(x.mass > 0) || !(x.inertia[0] > 0) || !(x.inertia[1] > 0) ||
+                !(x.inertia[2] > 0))
+                return LBM_E_ARG;
+        }
+        for (int k = 0; k < ns; ++k) {
+            const lbm_spring &x = springs[(size_t)s * ns + k];
+            if (x.i < 0 || x.i >= nb || x.j < 0 || x.j >= nb || x.i == x.j || !(x.rest_len >= 0)) return LBM_E_ARG;
+        }
+        for (int d = 0; d < nd; ++d) {
+            const lbm_drive &x = drives[(size_t)s * nd + d];
+            if (x.left < 0 || x.left >= nb || x.right < 0 || x.right >= nb || x.middle < 0 || x.middle >= nb ||
+                !(x.period > 0))
+                return LBM_E_ARG;
+        }
+    }
+    std::vector<DevBody> db((size_t)nsys * nb);
+    std::vector<DevSpring> ds((size_t)nsys * ns);
+    std::vector<DevDrive> dd((size_t)nsys * nd);
+    for (size_t q = 0; q < db.size(); ++q) db[q] = to_dev(bodies[q]);
+    for (size_t q = 0; q < ds.size(); ++q)
+        ds[q] = {springs[q].i, springs[q].j, springs[q].k, springs[q].gamma, springs[q].rest_len};
+    for (size_t q = 0; q < dd.size(); ++q)
+        dd[q] = {drives[q].left, drives[q].middle, drives[q].right, drives[q].gate_lagged, drives[q].amplitude,
+                 drives[q].period, drives[q].phase_lag, (long long)drives[q].off_left, (long long)drives[q].off_right};
+    DevBody *g_bodies = nullptr;
+    DevSpring *g_springs = nullptr;
+    DevDrive *g_drives = nullptr;
+    BoxDesc *g_desc = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = LBM_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && rc == LBM_OK) rc = LBM_E_HIP;
+        return rc == LBM_OK;
+    };
+    if (ok(hipMalloc(&g_bodies, sizeof(DevBody) * db.size())) &&
+        ok(hipMalloc(&g_springs, sizeof(DevSpring) * std::max<size_t>(ds.size(), 1))) &&
+        ok(hipMalloc(&g_drives, sizeof(DevDrive) * std::max<size_t>(dd.size(), 1))) &&
+        ok(hipMalloc(&g_desc, sizeof(BoxDesc) * nsys))) {
+        std::vector<BoxDesc> desc(nsys);
+        for (int s = 0; s < nsys; ++s) {
+            BoxDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.nb = nb;
+            d.ns = ns;
+            d.nd = nd;
+            d.bodies = g_bodies + (size_t)s * nb;
+            d.springs = g_springs + (size_t)s * ns;
+            d.drives = g_drives + (size_t)s * nd;
+            d.traj = traj ? traj + (size_t)s * traj_cap * nb * 16 : nullptr;
+            d.traj_cap = traj ? traj_cap : 0;
+            desc[s] = d;
+        }
+        if (ok(hipMemcpyAsync(g_bodies, db.data(), sizeof(DevBody) * db.size(), hipMemcpyHostToDevice, st)) &&
+            (ds.empty() || ok(hipMemcpyAsync(g_springs, ds.data(), sizeof(DevSpring) * ds.size(),
+                                             hipMemcpyHostToDevice, st))) &&
+            (dd.empty() || ok(hipMemcpyAsync(g_drives, dd.data(), sizeof(DevDrive) * dd.size(),
+                                             hipMemcpyHostToDevice, st))) &&
+            ok(hipMemcpyAsync(g_desc, desc.data(), sizeof(BoxDesc) * nsys, hipMemcpyHostToDevice, st))) {
+            hipLaunchKernelGGL(vacuum_kernel, dim3(nsys), dim3(kCoupleThreads), 0, st, g_desc, (long long)nsteps);
+            if (ok(hipGetLastError()) &&
+                ok(hipMemcpyAsync(db.data(), g_bodies, sizeof(DevBody) * db.size(), hipMemcpyDeviceToHost, st)) &&
+                ok(hipMemcpyAsync(desc.data(), g_desc, sizeof(BoxDesc) * nsys, hipMemcpyDeviceToHost, st)) &&
+                ok(hipStreamSynchronize(st))) {
+                for (int s = 0; s < nsys; ++s)
+                    if (desc[s].status == LBM_E_UNSTABLE) rc = LBM_E_UNSTABLE;
+                if (out)
+                    for (size_t q = 0; q < db.size(); ++q) out[q] = from_dev(db[q]);
+            }
+        }
+    }
+    if (g_bodies || g_desc) (void)hipStreamSynchronize(st);
+    (void)hipFree(g_bodies);
+    (void)hipFree(g_springs);
+    (void)hipFree(g_drives);
+    (void)hipFree(g_desc);
+    return rc;
+}
+
 int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,
                     void *stream) {
     if (!src || !dst || bytes <= 0 || (bytes % 16) != 0 || blocks_per_cu < 0) return LBM_E_ARG;

@@ -269,3 +269,33 @@ class Sim(BatchSim):
             self.ctx, int(steps), int(checkpoint_every), w.ctypes.data_as(C.POINTER(C.c_double)),
             C.byref(J), g))
         return J.value, np.array(list(g))
+
+
+def vacuum_run(cases, steps, traj_cap=0, device="cuda:0"):
+    """Integrator-only runs of the swimmers of ``cases`` (one system each, all
+    with the same numbers of bodies, springs and drives) for ``steps`` steps
+    through ``lbm_vacuum_run``.  Returns (final body states per system, the
+    trajectory ring as numpy (systems, traj_cap, bodies, 16) or None)."""
+    lib = _abi.load()
+    nb, ns, nd = len(cases[0].bodies), len(cases[0].springs), len(cases[0].drives)
+    if any((len(c.bodies), len(c.springs), len(c.drives)) != (nb, ns, nd) for c in cases):
+        raise ValueError("every system needs the same numbers of bodies, springs and drives")
+    bodies = (LbmBody * (nb * len(cases)))(*[_body_struct(b) for c in cases for b in c.bodies])
+    springs = (LbmSpring * max(ns * len(cases), 1))(*[LbmSpring(s.i, s.j, s.k, s.gamma, s.rest_len)
+                                                       for c in cases for s in c.springs])
+    drives = (LbmDrive * max(nd * len(cases), 1))(*[LbmDrive(d.left, d.middle, d.right, int(d.gate_lagged),
+                                                             d.amplitude, d.period, d.phase_lag, d.off_left,
+                                                             d.off_right) for c in cases for d in c.drives])
+    out = (LbmBody * (nb * len(cases)))()
+    dev = torch.device(device)
+    traj = torch.zeros((len(cases), traj_cap, nb, _abi.TRAJ_DOUBLES), dtype=torch.float64,
+                       device=dev) if traj_cap else None
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        rc = lib.lbm_vacuum_run(bodies, nb, springs, ns, drives, nd, len(cases), int(steps),
+                                C.c_void_p(traj.data_ptr()) if traj is not None else None, int(traj_cap), out,
+                                C.c_void_p(stream))
+    if rc != _abi.LBM_OK:
+        raise _abi.LbmError(rc, "lbm_vacuum_run failed")
+    states = [[_body_dict(out[s * nb + b]) for b in range(nb)] for s in range(len(cases))]
+    return states, (traj.cpu().numpy() if traj is not None else None)

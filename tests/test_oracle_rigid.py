@@ -10,37 +10,15 @@ import pytest
 from scipy.integrate import solve_ivp
 
 import workloads as W
-from oracle import rigid
-from oracle.sim import _body_state
+from oracle import rigid, vacuum
 
 
 def _vacuum(case, steps):
-    bodies = [_body_state(b, float) for b in case.bodies]
-    for b in bodies:
-        b["X"] = [b["anchor"][k] + b["D"][k] for k in range(3)]
-    springs = [dict(i=s.i, j=s.j, k=s.k, gamma=s.gamma, rest_len=s.rest_len) for s in case.springs]
-    drives = [dict(left=d.left, middle=d.middle, right=d.right, amplitude=d.amplitude,
-                   period=d.period, phase_lag=d.phase_lag, gate_lagged=d.gate_lagged,
-                   off_left=d.off_left, off_right=d.off_right) for d in case.drives]
-    hist = []
-    for n in range(steps):
-        Fd = rigid.driving_forces(drives, n, len(bodies))
-        Fs = rigid.spring_forces(springs, bodies)
-        for b, body in enumerate(bodies):
-            Ft = [(0.0 + Fd[b][k]) + Fs[b][k] for k in range(3)]
-            rigid.integrate(body, Ft, [0.0, 0.0, 0.0])
-        hist.append([[body["D"][0], body["V"][0]] for body in bodies])
-    return np.array(hist)  # (steps, bodies, 2)
+    return vacuum.run(case, steps)
 
 
 def _linear_system(m, k, g):
-    # bodies (mid, left, right); springs (left, mid) and (right, mid); 1-D along x
-    K = np.array([[-2 * k, k, k], [k, -k, 0.0], [k, 0.0, -k]])
-    G = np.array([[-2 * g, g, g], [g, -g, 0.0], [g, 0.0, -g]])
-    I = np.eye(3)
-    # state s = (D, V):  V' = V + (K D + G V + F)/m,  D' = D + V'
-    M = np.block([[I + K / m, I + G / m], [K / m, I + G / m]])
-    return M
+    return vacuum.linear_system(m, k, g)
 
 
 def test_vacuum_matches_exact_discrete_solution():
@@ -68,6 +46,8 @@ def test_vacuum_matches_exact_discrete_solution():
         s = np.real(s_hat * np.exp(1j * w * n)) + hom
         got = np.concatenate([hist[n - 1, :, 0], hist[n - 1, :, 1]])
         assert np.allclose(got, s, rtol=0, atol=1e-12 * np.abs(s).max())
+        # the oracle's own closed form, written independently of the test's
+        assert np.allclose(vacuum.exact(m, k, g, a, w, psi, n), s, rtol=0, atol=1e-12 * np.abs(s).max())
 
 
 def test_vacuum_total_momentum_stays_zero():

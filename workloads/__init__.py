@@ -349,6 +349,43 @@ def paper_flow_channel(swimmers: int = 3, storage: str = "f32") -> Case:
                 drives=drives, steps=one.steps, storage=storage, force_average=True)
 
 
+# Sec. 4: range of the spring constant in the resonance sweep (kg/s^2)
+VACUUM_K_RANGE = (4.76813e-3, 0.181309)
+
+
+def vacuum_sweep(n: int = 38, steps: int = 1_000_000, amplitude: float = 1e-6) -> List[Case]:
+    """The integrator-only runs of Sec. 4 (Fig. vacuumVal2): the three-sphere
+    swimmer in vacuum with the left, middle and right spheres at x = 25, 50,
+    75 and rest lengths 25, the lattice mass 400 of the design study, the
+    driving period T = 28116 with the right force delayed by T/4 (ungated and
+    never switched off, so that the drive is a pure sinusoid) and the damping
+    ratio D = 0.07 of Eq. dampingFactor in every run.  The n spring
+    constants put omega_0 / omega = sqrt(k / m) / omega evenly over the
+    printed range of k (0.316 ... 1.950).  The box is nominal: no fluid.
+
+    The drive amplitude of these runs is not given.  At the design study's
+    a = 4.19e-3 the softest springs would stretch by up to about 2000 cells
+    and the bodies would pass through one another, outside the linear model
+    of Sec. 4; the amplitude plotted, A / a, does not depend on a while the
+    motion stays linear, so a = 1e-6 keeps every arm within a cell of its
+    rest length."""
+    m, k_paper, _, _ = paper_units()
+    a = amplitude
+    T = PAPER_SI["period"]
+    w = 2.0 * math.pi / T
+    per_si = k_paper / PAPER_SI["k"]          # lattice stiffness per kg/s^2
+    lo, hi = (math.sqrt(k * per_si / m) / w for k in VACUUM_K_RANGE)
+    cases = []
+    for ratio in np.linspace(lo, hi, n):
+        k = m * (ratio * w) ** 2
+        gamma = 2.0 * 0.07 * math.sqrt(m * k)
+        b, s, d = swimmer((50.0, 50.0, 50.0), r=4.0, l0=(25.0, 25.0), k=k, gamma=gamma, mass=m, amplitude=a,
+                          period=float(T), phase_lag=math.pi / 2)
+        cases.append(Case(f"vacuum_w0_{ratio:.4f}", 100, 100, 100, 1.0, bodies=b, springs=s, drives=[d],
+                          steps=steps))
+    return cases
+
+
 def random_small(seed: int, storage: str = "f64") -> Case:
     """A small random box with one to three free, kinematic or rotation-locked
     spheres/capsules,
