@@ -199,8 +199,9 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     if (!params || nbox < 1 || nbox > 65535) return LBM_E_ARG;
     lbm_ctx *c = new lbm_ctx();
     c->storage = params[0].storage;
-    // streaming hints pay off for the 16-bit formats only (measured on the
-    // 256x128x128 sweep: FP16S/BF16S 4-7% faster, FP32/FP64 5-15% slower)
+    // non-temporal loads pay off for the 16-bit formats (FP16S sweep of the
+    // 256x128x128 box: 91 -> 70 us) and not for FP32/FP64 (no change, FP64 2%
+    // slower); non-temporal stores were slower for every format
     c->nontemporal = (c->storage == LBM_F16S || c->storage == LBM_BF16S) ? 1 : 0;
     c->stream = (hipStream_t)params[0].stream;
     for (int b = 0; b < nbox; ++b) {
@@ -1177,9 +1178,15 @@ int lbm_flow_average_begin(lbm_ctx *c, int32_t box, int32_t every) {
     HostBox &h = c->boxes[box];
     if (every > 0) {
         if (!h.flow_sum) {
-            if (hipMalloc(&h.flow_sum, sizeof(double) * 3 * (size_t)h.N) != hipSuccess ||
-                hipMalloc(&h.flow_count, sizeof(int) * (size_t)h.N) != hipSuccess)
+            double *sum = nullptr;
+            int *cnt = nullptr;
+            if (hipMalloc(&sum, sizeof(double) * 3 * (size_t)h.N) != hipSuccess ||
+                hipMalloc(&cnt, sizeof(int) * (size_t)h.N) != hipSuccess) {
+                (void)hipFree(sum);
                 return fail(c, LBM_E_HIP, "out of device memory for the flow average");
+            }
+            h.flow_sum = sum;
+            h.flow_count = cnt;
         }
         HIP_TRY(c, hipMemsetAsync(h.flow_sum, 0, sizeof(double) * 3 * (size_t)h.N, c->stream));
         HIP_TRY(c, hipMemsetAsync(h.flow_count, 0, sizeof(int) * (size_t)h.N, c->stream));

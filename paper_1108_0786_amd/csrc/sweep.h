@@ -188,7 +188,7 @@ __device__ __forceinline__ void flow_sample(const BoxDesc &B, int cell, const C 
 // Interior push: no wall and no body among the neighbours.  off_p / off_m
 // are the linear offsets of the +1 / -1 neighbour along each axis (with the
 // periodic wrap already applied).
-template <typename S, int A, bool NT>
+template <typename S, int A>
 struct PushFast {
     template <typename P>
     static __device__ __forceinline__ void run(P dst, long long stride, int cell, const int *off_p,
@@ -196,12 +196,12 @@ struct PushFast {
         const int o = (ex(A) > 0 ? off_p[0] : ex(A) < 0 ? off_m[0] : 0) +
                       (ey(A) > 0 ? off_p[1] : ey(A) < 0 ? off_m[1] : 0) +
                       (ez(A) > 0 ? off_p[2] : ez(A) < 0 ? off_m[2] : 0);
-        Storage<S>::template store<NT>(dst + (size_t)A * stride, (size_t)(unsigned)(cell + o), f[A], scale);
-        PushFast<S, A + 1, NT>::run(dst, stride, cell, off_p, off_m, f, scale);
+        Storage<S>::store(dst + (size_t)A * stride, (size_t)(unsigned)(cell + o), f[A], scale);
+        PushFast<S, A + 1>::run(dst, stride, cell, off_p, off_m, f, scale);
     }
 };
-template <typename S, bool NT>
-struct PushFast<S, 19, NT> {
+template <typename S>
+struct PushFast<S, 19> {
     template <typename P>
     static __device__ __forceinline__ void run(P, long long, int, const int *, const int *,
                                                const typename Storage<S>::C *, float) {}
@@ -219,7 +219,7 @@ struct XLanes {
     bool from_left, from_right, own_px, own_mx, fast;
 };
 
-template <typename S, int A, bool NT>
+template <typename S, int A>
 struct PushLanes {
     template <typename P>
     static __device__ __forceinline__ void run(P dst, long long stride, int cell, const int *off_p,
@@ -230,21 +230,21 @@ struct PushLanes {
                         (ez(A) > 0 ? off_p[2] : ez(A) < 0 ? off_m[2] : 0);
         P base = dst + (size_t)A * stride;
         if constexpr (ex(A) == 0) {
-            if (x.fast) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), f[A], scale);
+            if (x.fast) St::store(base, (size_t)(unsigned)(cell + oyz), f[A], scale);
         } else if constexpr (ex(A) > 0) {
             const auto v = __shfl_up(f[A], 1);
-            if (x.from_left) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), v, scale);
-            if (x.own_px) St::template store<NT>(base, (size_t)(unsigned)(cell + off_p[0] + oyz), f[A], scale);
+            if (x.from_left) St::store(base, (size_t)(unsigned)(cell + oyz), v, scale);
+            if (x.own_px) St::store(base, (size_t)(unsigned)(cell + off_p[0] + oyz), f[A], scale);
         } else {
             const auto v = __shfl_down(f[A], 1);
-            if (x.from_right) St::template store<NT>(base, (size_t)(unsigned)(cell + oyz), v, scale);
-            if (x.own_mx) St::template store<NT>(base, (size_t)(unsigned)(cell + off_m[0] + oyz), f[A], scale);
+            if (x.from_right) St::store(base, (size_t)(unsigned)(cell + oyz), v, scale);
+            if (x.own_mx) St::store(base, (size_t)(unsigned)(cell + off_m[0] + oyz), f[A], scale);
         }
-        PushLanes<S, A + 1, NT>::run(dst, stride, cell, off_p, off_m, f, scale, x);
+        PushLanes<S, A + 1>::run(dst, stride, cell, off_p, off_m, f, scale, x);
     }
 };
-template <typename S, bool NT>
-struct PushLanes<S, 19, NT> {
+template <typename S>
+struct PushLanes<S, 19> {
     template <typename P>
     static __device__ __forceinline__ void run(P, long long, int, const int *, const int *,
                                                const typename Storage<S>::C *, float, const XLanes &) {}
@@ -330,13 +330,13 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
         x.from_right = valid && right_row && right_fast;
         x.own_px = fast && !(right_row && right_fast);
         x.own_mx = fast && !(left_row && left_fast);
-        if (fast) St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
-        PushLanes<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale, x);
+        if (fast) St::store(dst, (size_t)cell, f[0], B.scale);
+        PushLanes<S, 1>::run(dst, stride, cell, off_p, off_m, f, B.scale, x);
     } else {
         // 2-byte storage: each lane pushes its own values
         if (fast) {
-            St::template store<NT>(dst, (size_t)cell, f[0], B.scale);
-            PushFast<S, 1, NT>::run(dst, stride, cell, off_p, off_m, f, B.scale);
+            St::store(dst, (size_t)cell, f[0], B.scale);
+            PushFast<S, 1>::run(dst, stride, cell, off_p, off_m, f, B.scale);
         }
     }
     if (fast || !valid || !fluid) return;

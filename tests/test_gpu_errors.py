@@ -1,0 +1,160 @@
+"""Error paths and edge cases of the C-ABI, on the GPU.
+
+Every invalid argument is rejected on the host with its documented code
+before any device work; calls made in the wrong state return LBM_E_STATE.
+Edge cases run against the oracle: a box without bodies (plain LBGK between
+walls) and relaxation times near the stability limit and far above 1."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import OracleSim
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1108_0786_amd import _abi
+    return _abi, _abi.load()
+
+
+def _init_rc(case, **changes):
+    """lbm_init on a box built like the binding's, with fields overridden."""
+    from paper_1108_0786_amd.sim import _Box
+    abi, lib = _lib()
+    box = _Box(case, "f32", torch.device("cuda:0"), 0, 0)
+    p = box.params
+    for key, val in changes.items():
+        if key == "pop":
+            p.pop[0], p.pop[1] = val
+        else:
+            setattr(p, key, val)
+    ctx = C.c_void_p()
+    rc = lib.lbm_init(C.byref(p), C.byref(ctx))
+    if ctx:
+        lib.lbm_destroy(ctx)
+    return rc
+
+
+@pytest.mark.parametrize("changes", [
+    dict(tau=0.5), dict(tau=float("nan")), dict(nx=2), dict(storage=7), dict(periodic_mask=8),
+    dict(flags=None), dict(reserved=1), dict(force_average=2), dict(stride=100),
+    dict(traj=1, traj_cap=0),                   # a trajectory pointer without a capacity (never dereferenced)
+])
+def test_invalid_parameters_are_rejected(changes):
+    abi, _ = _lib()
+    case = W.plain_f64_small()
+    print(f"[gpu] invalid parameters {changes}", flush=True)
+    assert _init_rc(case, **changes) == abi.LBM_E_ARG
+
+
+def test_equal_population_buffers_are_rejected():
+    abi, _ = _lib()
+    case = W.plain_f64_small()
+    t = torch.zeros(19 * case.ncells, dtype=torch.float32, device="cuda:0")
+    assert _init_rc(case, pop=(t.data_ptr(), t.data_ptr())) == abi.LBM_E_ARG
+
+
+def _set_bodies_error(case):
+    from paper_1108_0786_amd.sim import Sim
+    abi, _ = _lib()
+    with pytest.raises(abi.LbmError) as e:
+        Sim(case, storage="f32")
+    return e.value.code
+
+
+def test_invalid_bodies_springs_and_drives_are_rejected():
+    abi, _ = _lib()
+    print("[gpu] invalid bodies, springs, drives", flush=True)
+    case = W.plain_f64_small()
+    case.springs[0].i = 7
+    assert _set_bodies_error(case) == abi.LBM_E_ARG
+    case = W.plain_f64_small()
+    case.drives[0].period = 0.0
+    assert _set_bodies_error(case) == abi.LBM_E_ARG
+    case = W.plain_f64_small()
+    case.bodies = [W.make_body(W.SPHERE, 1.0, 1.0, (3.0 + 2.9 * n, 16.0, 16.0)) for n in range(17)]
+    case.springs, case.drives = [], []
+    assert _set_bodies_error(case) == abi.LBM_E_ARG      # more than 16 bodies
+    case = W.plain_f64_small()
+    case.bodies[0].anchor = (24.0, 2.5, 16.0)            # r = 3 reaches through the wall at y = 0
+    assert _set_bodies_error(case) == abi.LBM_E_OVERLAP
+
+
+def test_calls_in_the_wrong_state():
+    from paper_1108_0786_amd.sim import Sim
+    abi, lib = _lib()
+    print("[gpu] wrong-state calls and tuning errors", flush=True)
+    sim = Sim(W.plain_f64_small(), storage="f64")
+    out = torch.empty(3 * sim.boxes[0].N, dtype=torch.float64, device="cuda:0")
+    assert lib.lbm_flow_average_get(sim.ctx, 0, C.c_void_p(out.data_ptr()), None) == abi.LBM_E_STATE
+    assert lib.lbm_flow_average_begin(sim.ctx, 0, -1) == abi.LBM_E_ARG
+    assert lib.lbm_flow_average_begin(sim.ctx, 1, 1) == abi.LBM_E_ARG      # no box 1
+    sim.flow_average_begin(1)
+    w = (C.c_double * 3)(1.0, 0.0, 0.0)
+    J, g = C.c_double(), (C.c_double * 3)()
+    assert lib.lbm_adjoint(sim.ctx, 10, 5, w, C.byref(J), g) == abi.LBM_E_STATE
+    sim.flow_average_begin(0)
+    assert lib.lbm_tune(sim.ctx, 99, 1) == abi.LBM_E_ARG
+    assert lib.lbm_tune(sim.ctx, abi.TUNE["block"], 100) == abi.LBM_E_ARG
+    assert lib.lbm_tune(sim.ctx, abi.TUNE["coop_remap"], 2) == abi.LBM_E_ARG
+    assert lib.lbm_step(sim.ctx, -1) == abi.LBM_E_ARG
+    sim.step(5)
+    sim.status()
+    sim.close()
+
+
+def test_invalid_vacuum_runs_are_rejected():
+    from paper_1108_0786_amd.sim import vacuum_run
+    abi, lib = _lib()
+    print("[gpu] invalid vacuum runs", flush=True)
+    good = W.vacuum_sweep(n=2, steps=10)
+    bad = W.vacuum_sweep(n=1, steps=10)[0]
+    bad.springs[1].j = 5
+    with pytest.raises(abi.LbmError) as e:
+        vacuum_run([good[0], bad], 10)
+    assert e.value.code == abi.LBM_E_ARG
+    bad = W.vacuum_sweep(n=1, steps=10)[0]
+    bad.drives[0].period = -1.0
+    with pytest.raises(abi.LbmError) as e:
+        vacuum_run([bad], 10)
+    assert e.value.code == abi.LBM_E_ARG
+    assert lib.lbm_vacuum_run(None, 3, None, 0, None, 0, 1, 10, None, 0, None, None) == abi.LBM_E_ARG
+    states, _ = vacuum_run(good, 0)                      # zero steps: the bodies come back unchanged
+    assert all(b["D"] == [0.0, 0.0, 0.0] for s in states for b in s)
+
+
+def _parity(case, steps, df0):
+    from paper_1108_0786_amd.sim import Sim
+    orc = OracleSim(case, df0=df0).run(steps)
+    sim = Sim(case, storage="f64", df0=df0, traj_cap=max(steps, 1))
+    sim.step(steps)
+    sim.status()
+    err = np.abs(sim.populations() - orc.populations()).max() / np.abs(orc.populations()).max()
+    sim.close()
+    return err
+
+
+def test_box_without_bodies():
+    case = W.Case("empty_24x20x18", 24, 20, 18, 0.8, steps=60)
+    df0 = W.initial_populations(case, seed=3, amp=1e-3)
+    err = _parity(case, 60, df0)
+    print(f"[gpu] box without bodies: dF error {err:.1e}", flush=True)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("tau", [0.51, 3.0])
+def test_relaxation_time_extremes(tau):
+    # the swimmer moves with the two-step force mean: with the plain coupling
+    # its period-2 mode grows at tau = 0.51 (in the oracle |dF| goes from
+    # 1e-4 to 0.7 in 80 steps), and two runs that round differently part
+    case = W.plain_f64_small()
+    case.tau = tau
+    case.force_average = True
+    df0 = W.initial_populations(case, seed=9, amp=1e-4)
+    err = _parity(case, 80, df0)
+    print(f"[gpu] tau {tau}: dF error {err:.1e}", flush=True)
+    assert err < 1e-12

@@ -82,30 +82,66 @@ def test_flow_sampling_leaves_the_run_unchanged():
     other.close()
 
 
-def _paper_run(swimmers):
+@pytest.fixture(scope="module")
+def channels():
+    """The two channels of Fig. flowfields13, each advanced a period at a time
+    by the tests below (so that the long runs report progress)."""
+    state = {}
+    yield state
+    for st in state.values():
+        if st["sim"] is not None:
+            st["sim"].close()
+
+
+def _paper_state(channels, swimmers):
     from paper_1108_0786_amd.sim import Sim
-    case = W.paper_flow_channel(swimmers, "f32")
-    T = W.PAPER_SI["period"]
-    total = case.steps
-    print(f"[gpu] flow field {case.name}: {total} steps FP32, average over steps 0..{5 * T - 1}", flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim = Sim(case, storage="f32", traj_cap=T + 1)
-    sim.flow_average_begin(1)
-    for p in range(5):
-        sim.step(T)
-        sim.status()
-        print(f"[gpu] flow field {swimmers}: period {p + 1} done", flush=True)
-    sim.flow_average_begin(0)
-    tr = sim.trajectory()             # the last driven period, steps 4T - 1 .. 5T - 1
-    tr = tr[np.argsort(tr[:, 0, 15])]
-    sim.step(total - 5 * T)           # free relaxation, as in the paper's runs
+    if swimmers not in channels:
+        case = W.paper_flow_channel(swimmers, "f32")
+        T = W.PAPER_SI["period"]
+        print(f"[gpu] flow field {case.name}: {case.steps} steps FP32, average over steps 0..{5 * T - 1}",
+              flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim = Sim(case, storage="f32", traj_cap=T + 1)
+        sim.flow_average_begin(1)
+        channels[swimmers] = dict(sim=sim, case=case, T=T, periods=0, t0=t0, seconds=None, tr=None)
+    return channels[swimmers]
+
+
+def _advance(st):
+    """One more period: five driven ones while the average is taken, then the
+    free relaxation to the paper's 196812 steps (7 periods)."""
+    sim, T = st["sim"], st["T"]
+    sim.step(T)
     sim.status()
-    mean, count = sim.flow_average()
-    torch.cuda.synchronize()
-    seconds = time.perf_counter() - t0
-    sim.close()
-    return case, mean, count, tr, seconds
+    st["periods"] += 1
+    if st["periods"] == 5:
+        sim.flow_average_begin(0)
+        tr = sim.trajectory()         # the last driven period, steps 4T - 1 .. 5T - 1
+        st["tr"] = tr[np.argsort(tr[:, 0, 15])]
+    if st["periods"] == st["case"].steps // T:
+        torch.cuda.synchronize()
+        st["seconds"] = time.perf_counter() - st["t0"]
+    print(f"[gpu] flow field {st['case'].name}: period {st['periods']} done", flush=True)
+
+
+def _paper_run(channels, swimmers):
+    st = _paper_state(channels, swimmers)
+    total = st["case"].steps // st["T"]
+    while st["periods"] < total:
+        _advance(st)
+    if st["sim"] is not None:
+        st["mean"], st["count"] = st["sim"].flow_average()
+        st["sim"].close()
+        st["sim"] = None
+    return st["case"], st["mean"], st["count"], st["tr"], st["seconds"]
+
+
+@pytest.mark.parametrize("swimmers,period", [(3, p) for p in range(1, 8)] + [(1, p) for p in range(1, 8)])
+def test_paper_flow_channel_period(channels, swimmers, period):
+    st = _paper_state(channels, swimmers)
+    while st["periods"] < period:
+        _advance(st)
 
 
 def _mirror_err(mean, axis, flip_component, keep=None):
@@ -122,8 +158,8 @@ def _mirror_err(mean, axis, flip_component, keep=None):
 
 
 @pytest.mark.parametrize("swimmers", [3, 1])
-def test_paper_flow_field(swimmers):
-    case, mean, count, tr, seconds = _paper_run(swimmers)
+def test_paper_flow_field(channels, swimmers):
+    case, mean, count, tr, seconds = _paper_run(channels, swimmers)
     T = W.PAPER_SI["period"]
     cells = case.nx * case.ny * case.nz
     vmax = np.abs(mean).max()

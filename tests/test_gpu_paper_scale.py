@@ -89,18 +89,38 @@ def _analyse(design, case, tr, T):
 
 
 @pytest.fixture(scope="module")
-def study():
+def batch():
+    """The seventeen channels in one batch, advanced a period at a time by
+    the tests below (each period a test of its own, so that the run reports
+    progress)."""
     from paper_1108_0786_amd.sim import BatchSim
     cases = [W.paper_design(d, "f32") for d in DESIGNS]
     T = W.PAPER_SI["period"]
     print(f"[gpu] design study: {len(cases)} swimmers, 200x100x100 each, {5 * T} steps FP32", flush=True)
-    sim = BatchSim(cases, storage="f32", traj_cap=T + 1)
-    for p in range(5):
-        sim.step(T)
-        sim.status()
-        print(f"[gpu] design study: period {p + 1} done", flush=True)
+    state = dict(sim=BatchSim(cases, storage="f32", traj_cap=T + 1), cases=cases, T=T, periods=0)
+    yield state
+    state["sim"].close()
+
+
+def _advance(batch):
+    batch["sim"].step(batch["T"])
+    batch["sim"].status()
+    batch["periods"] += 1
+    print(f"[gpu] design study: period {batch['periods']} done", flush=True)
+
+
+@pytest.mark.parametrize("period", range(1, 6))
+def test_design_study_period(batch, period):
+    while batch["periods"] < period:
+        _advance(batch)
+
+
+@pytest.fixture(scope="module")
+def study(batch):
+    while batch["periods"] < 5:
+        _advance(batch)
+    sim, cases, T = batch["sim"], batch["cases"], batch["T"]
     out = {d: _analyse(d, c, sim.trajectory(i), T) for i, (d, c) in enumerate(zip(DESIGNS, cases))}
-    sim.close()
     for d in DESIGNS:
         r = out[d]
         u_print, err, par = _printed(d)
