@@ -53,14 +53,17 @@ def _body_dict(s):
 
 def padded_stride(n, pad=None):
     """Elements between consecutive directions' arrays: N rounded up to 256
-    elements plus ``pad`` (default 4160 = 65 * 64), so that the 19 streams of a
-    sweep do not sit at a power-of-two spacing in HBM."""
+    elements plus ``pad`` (default 1024), so that the 19 streams of a sweep do
+    not sit at a power-of-two spacing in HBM.  On the 256x128x128 box any pad
+    from 512 to 3072 elements gives the same sweep time within 1%; 1024 is 2%
+    (FP32) and 4% (FP64) faster than 4160 and the same for the 16-bit
+    formats."""
     if pad is None:
         pad = DEFAULT_PAD
     return (n + 255) // 256 * 256 + pad if pad else n
 
 
-DEFAULT_PAD = 4160
+DEFAULT_PAD = 1024
 
 
 class _Box:

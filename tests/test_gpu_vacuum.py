@@ -4,6 +4,12 @@ rigid-body step of the coupled path with no fluid, for many systems at once.
 Parity: trajectories of a spread of the resonance-sweep systems against the
 oracle's step-by-step vacuum run, to 1e-12 of the largest displacement.
 
+The run of Fig. positionPlot (design-study springs and driving, switched off
+after five periods): the whole trajectory against the oracle, the centroid at
+rest throughout, and the time at which the arms are back at their rest
+lengths against the caption's t3 of about 179000 steps (read as the arms
+staying within 0.1% of their driven amplitude: flat in the figure).
+
 The sweep of Fig. vacuumVal2: 38 systems (damping ratio 0.07, omega_0 / omega
 from 0.316 to 1.950) for the paper's 10^6 steps.  Asserted: the final states
 equal the closed-form solution of the discrete recurrence from rest
@@ -108,3 +114,27 @@ def test_vacuum_resonance_sweep():
     assert len(peaks) == 2
     assert abs(ratios[peaks[0]] - 1.0 / math.sqrt(3.0)) < 1.5 * step
     assert abs(ratios[peaks[1]] - 1.0) < 1.5 * step
+
+
+def test_position_plot_run():
+    from paper_1108_0786_amd.sim import vacuum_run
+    case = W.vacuum_position_plot()
+    n = case.steps
+    T = int(case.drives[0].period)
+    print(f"[gpu] vacuum run of Fig. positionPlot: {n} steps", flush=True)
+    _, traj = vacuum_run([case], n, traj_cap=n)
+    tr = traj[0][np.argsort(traj[0][:, 0, 15])]
+    assert np.array_equal(tr[:, 0, 15], np.arange(n))
+    ref = vacuum.run(case, n)
+    D = tr[:, :, 0]
+    err = np.abs(D - ref[:, :, 0]).max() / np.abs(ref[:, :, 0]).max()
+    # force neutrality: the driving forces and the springs sum to zero
+    drift = np.abs(D.mean(axis=1)).max()
+    arms = np.maximum(np.abs(D[:, 0] - D[:, 1]), np.abs(D[:, 2] - D[:, 0]))
+    amp = arms[4 * T:5 * T].max()
+    t3 = int(np.where(arms > 1e-3 * amp)[0][-1]) + 1
+    print(f"[gpu] positionPlot: error against the oracle {err:.1e}, centroid drift {drift:.1e}, driven arm "
+          f"amplitude {amp:.3f} cells, arms at rest (0.1%) from step {t3} (caption: about 179000)", flush=True)
+    assert err < 1e-12
+    assert drift < 1e-9 * amp
+    assert abs(t3 - 179000) < 0.05 * 179000

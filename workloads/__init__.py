@@ -386,6 +386,19 @@ def vacuum_sweep(n: int = 38, steps: int = 1_000_000, amplitude: float = 1e-6) -
     return cases
 
 
+def vacuum_position_plot() -> Case:
+    """The vacuum run of Fig. positionPlot (Sec. 4): the design study's
+    masses, springs and driving (gated right force, switched off at 5T and
+    5T + T/4) on spheres at x = 25, 50, 75 with rest lengths 25, for the
+    196812 steps of the caption.  The box is nominal: no fluid."""
+    m, k, gamma, a = paper_units()
+    T = PAPER_SI["period"]
+    b, s, d = swimmer((50.0, 50.0, 50.0), r=4.0, l0=(25.0, 25.0), k=k, gamma=gamma, mass=m, amplitude=a,
+                      period=float(T), phase_lag=math.pi / 2, gate_lagged=True, off_left=5 * T,
+                      off_right=5 * T + T // 4)
+    return Case("vacuum_position_plot", 100, 100, 100, 1.0, bodies=b, springs=s, drives=[d], steps=196812)
+
+
 def random_small(seed: int, storage: str = "f64") -> Case:
     """A small random box with one to three free, kinematic or rotation-locked
     spheres/capsules,
