@@ -49,45 +49,57 @@ __device__ __forceinline__ typename Storage<S>::C bounce_moving(const BoxDesc &B
     return (C)val;
 }
 
+// owner[A]: the body behind the link (cell, A), 0 for fluid; only near-body
+// cells look it up.  slot: the cell's next link record.
 template <typename S, int A>
 __device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, long long stride, int cell, int i,
-                                         int j, int k, bool near, typename Storage<S>::C v,
-                                         typename Storage<S>::C rho, int &nlink) {
+                                         int j, int k, const uint8_t *owner, typename Storage<S>::C v,
+                                         typename Storage<S>::C rho, int &slot) {
     using St = Storage<S>;
     int ti, tj, tk;
     if (!neighbour<A>(i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk)) {
         St::store(dst, (size_t)opp(A) * stride + cell, v, B.scale);
         return;
     }
-    const int tcell = ti + B.nx * (tj + B.ny * tk);
-    if (near) {
-        const int owner = B.flags[tcell] & kOwnerMask;
-        if (owner) {
-            const int slot = B.link_base[cell] + nlink;
-            ++nlink;
-            St::store(dst, (size_t)opp(A) * stride + cell,
-                      bounce_moving<S, A>(B, cell, owner, ti, tj, tk, v, rho, slot), B.scale);
-            return;
-        }
+    if (owner[A]) {
+        St::store(dst, (size_t)opp(A) * stride + cell,
+                  bounce_moving<S, A>(B, cell, owner[A], ti, tj, tk, v, rho, slot), B.scale);
+        ++slot;
+        return;
     }
-    St::store(dst, (size_t)A * stride + tcell, v, B.scale);
+    St::store(dst, (size_t)A * stride + (ti + B.nx * (tj + B.ny * tk)), v, B.scale);
 }
 
 template <typename S, int A>
 struct PushAll {
     static __device__ __forceinline__ void run(const BoxDesc &B, S *dst, long long stride, int cell, int i,
-                                               int j, int k, bool near, const typename Storage<S>::C *f,
-                                               typename Storage<S>::C rho, int &nlink) {
-        push_one<S, A>(B, dst, stride, cell, i, j, k, near, f[A], rho, nlink);
-        PushAll<S, A + 1>::run(B, dst, stride, cell, i, j, k, near, f, rho, nlink);
+                                               int j, int k, const uint8_t *owner,
+                                               const typename Storage<S>::C *f, typename Storage<S>::C rho,
+                                               int &slot) {
+        push_one<S, A>(B, dst, stride, cell, i, j, k, owner, f[A], rho, slot);
+        PushAll<S, A + 1>::run(B, dst, stride, cell, i, j, k, owner, f, rho, slot);
     }
 };
 template <typename S>
 struct PushAll<S, 19> {
-    static __device__ __forceinline__ void run(const BoxDesc &, S *, long long, int, int, int, int, bool,
-                                               const typename Storage<S>::C *, typename Storage<S>::C,
-                                               int &) {}
+    static __device__ __forceinline__ void run(const BoxDesc &, S *, long long, int, int, int, int,
+                                               const uint8_t *, const typename Storage<S>::C *,
+                                               typename Storage<S>::C, int &) {}
 };
+
+// Owners of the 18 neighbours of a near-body cell, loaded before any is
+// used so that their latencies overlap (a neighbour across a wall reads the
+// cell itself, which is fluid).
+__device__ __forceinline__ void neighbour_owners(const BoxDesc &B, int cell, int i, int j, int k, uint8_t *owner) {
+    int idx[19];
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        int ti, tj, tk;
+        idx[a] = neighbour_rt(a, i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk) ? ti + B.nx * (tj + B.ny * tk) : cell;
+    }
+#pragma unroll
+    for (int a = 1; a < 19; ++a) owner[a] = B.flags[idx[a]] & kOwnerMask;
+}
 
 // LBGK collision in deviation form: dF~ = dF + omega (dF_eq - dF),
 // dF_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].  Opposite directions
@@ -342,8 +354,13 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
     if (fast || !valid || !fluid) return;
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
     St::store(gdst, (size_t)cell, f[0], B.scale);
-    int nlink = 0;
-    PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, (fl & kNearBit) != 0, f, rho, nlink);
+    uint8_t owner[19] = {};
+    int slot = 0;
+    if (fl & kNearBit) {
+        neighbour_owners(B, cell, i, j, k, owner);
+        slot = B.link_base[cell];
+    }
+    PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, owner, f, rho, slot);
 }
 
 }  // namespace lbm
