@@ -95,11 +95,8 @@ __device__ __forceinline__ float bf16_to_float(uint16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }
 __device__ __forceinline__ uint16_t float_to_bf16(float f) {
-    // round to nearest even; NaN stays NaN
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    // round to nearest even, NaN stays NaN: one v_cvt_pk_bf16_f32 on gfx950
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 template <> struct Storage<bf16_t> {
     using C = float;

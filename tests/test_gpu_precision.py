@@ -57,3 +57,43 @@ def test_capsule_crop_against_oracle(design, storage):
     # error bound is twice the displacement bound on the scale max|D| / max|v|
     assert eV < 2.0 * b * max(1.0, dscale / np.abs(vo).max())
     sim.close()
+
+
+def _rne_expected(t, storage):
+    """float32 values t rounded to the 16-bit format, round to nearest even
+    (IEEE 754), back in float32."""
+    if storage == "f16s":
+        return t.astype(np.float16).astype(np.float32)
+    bits = t.view(np.uint32).astype(np.uint64)
+    r = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_storage_rounds_to_nearest_even(storage):
+    # a box without bodies: importing populations stores them in the 16-bit
+    # format (scaled by 2^16) and exporting reads them back, so the export
+    # shows the rounding; half the values sit exactly halfway between two
+    # representable numbers, where the tie must go to the even one
+    from paper_1108_0786_amd.sim import Sim
+    case = W.Case("round_trip", 16, 8, 8, 0.8)
+    n = 19 * case.ncells
+    rng = np.random.default_rng(5)
+    if storage == "bf16s":
+        hi = rng.integers(0x3A00, 0x3F00, n).astype(np.uint32) << 16       # bf16 numbers, about 5e-4 .. 0.5
+        low = np.where(np.arange(n) % 2 == 0, 0x8000, rng.integers(1, 0x10000, n)).astype(np.uint32)
+    else:
+        exp = rng.integers(117, 133, n).astype(np.uint32)                  # 2^-10 .. 2^5: normal in FP16
+        hi = (exp << 23) | (rng.integers(0, 1024, n).astype(np.uint32) << 13)   # FP16-representable
+        low = np.where(np.arange(n) % 2 == 0, 0x1000, rng.integers(1, 0x2000, n)).astype(np.uint32)
+    t = (hi | low).view(np.float32)
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0).astype(np.float32)
+    t = t * sign
+    df = (t.astype(np.float64) * 2.0 ** -16).reshape(19, case.nz, case.ny, case.nx)
+    print(f"[gpu] storage round trip {storage}", flush=True)
+    sim = Sim(case, storage=storage, shift_log2=16)
+    sim.import_populations(df)
+    got = sim.populations()
+    want = (_rne_expected(t, storage).astype(np.float64) * 2.0 ** -16).reshape(got.shape)
+    sim.close()
+    assert np.array_equal(got, want)
