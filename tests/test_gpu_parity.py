@@ -250,3 +250,41 @@ def test_capsule_clearance_uses_the_exact_shape():
     with pytest.raises(LbmError) as e:
         _sim(pair((c45, 0.0, 0.0, c45), y=8.5), storage="f32")
     assert e.value.code == LBM_E_OVERLAP
+
+
+def _sixteen_bodies():
+    # the library's maximum of 16 bodies: four rows of four spheres along x,
+    # springs between neighbours in each row, one drive per row; the rows'
+    # bodies are free, prescribed or rotation-locked in turn
+    bodies, springs, drives = [], [], []
+    for row, (y, z) in enumerate(((12.0, 12.0), (28.0, 12.0), (12.0, 28.0), (28.0, 28.0))):
+        base = len(bodies)
+        for n in range(4):
+            b = W.make_body(W.SPHERE, 3.0, W.bead_mass(3.0), (10.0 + 16.0 * n, y, z))
+            b.kinematic = (row + n) % 3 if n else 0
+            if b.kinematic == 1:
+                b.vel = (0.002, 0.0, 0.0)
+            bodies.append(b)
+        springs += [W.Spring(base + n + 1, base + n, 0.05, 0.01, 16.0) for n in range(3)]
+        drives.append(W.Drive(left=base, middle=base + 1, right=base + 2, amplitude=2e-4, period=100.0 + 20 * row,
+                              phase_lag=math.pi / 2))
+    return W.Case("sixteen_64x40x40", 64, 40, 40, 1.0, bodies=bodies, springs=springs, drives=drives, steps=60)
+
+
+def test_sixteen_bodies_fp64_parity():
+    case = _sixteen_bodies()
+    df0 = W.initial_populations(case, seed=31, amp=1e-4)
+    print(f"[gpu] {case.name}: {len(case.bodies)} bodies, {len(case.springs)} springs, {len(case.drives)} drives",
+          flush=True)
+    orc = OracleSim(case, df0=df0).run(case.steps)
+    sim = _sim(case, storage="f64", traj_cap=case.steps, df0=df0)
+    sim.step(case.steps)
+    sim.status()
+    _check_geometry(sim, orc)
+    Fo, To, Do = _oracle_traj(orc)
+    Fg, Tg, Dg = _gpu_traj(sim, case.steps)
+    eF, eD = _rel(Fg, Fo), _rel(Dg, Do)
+    eP = _rel(sim.populations(), orc.populations())
+    print(f"[gpu] sixteen bodies: F {eF:.2e} D {eD:.2e} dF {eP:.2e}", flush=True)
+    assert eF < 1e-12 and eD < 1e-12 and eP < 1e-12
+    sim.close()
