@@ -221,8 +221,8 @@ def main():
     ap.add_argument("--batch-periods", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the swimmer step is built and timed on a single "
-              "MI355X (multi-GPU slab decomposition is a design, not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only: the swimmer step runs and is timed on a single "
+              "MI355X; the slab decomposition over several GPUs is designed, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import workloads as W
