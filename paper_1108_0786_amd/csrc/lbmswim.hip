@@ -199,10 +199,10 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     if (!params || nbox < 1 || nbox > 65535) return LBM_E_ARG;
     lbm_ctx *c = new lbm_ctx();
     c->storage = params[0].storage;
-    // non-temporal loads pay off for the 16-bit formats (FP16S sweep of the
-    // 256x128x128 box: 91 -> 70 us) and not for FP32/FP64 (no change, FP64 2%
-    // slower); non-temporal stores were slower for every format
-    c->nontemporal = (c->storage == LBM_F16S || c->storage == LBM_BF16S) ? 1 : 0;
+    // non-temporal loads pay off for every format but FP64 (sweep of the
+    // 256x128x128 box: FP32 129 -> 119 us, FP16S and BF16S 81-88 -> 65 us,
+    // FP64 242 -> 247 us); non-temporal stores were slower for every format
+    c->nontemporal = c->storage == LBM_F64 ? 0 : 1;
     c->stream = (hipStream_t)params[0].stream;
     for (int b = 0; b < nbox; ++b) {
         int rc = validate_params(c, params[b]);
