@@ -268,9 +268,10 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *   LBM_TUNE_FULL_REMAP   1: map the bodies every step even when no cell can
  *                         have changed side (default 0; results are identical)
  *   LBM_TUNE_NONTEMPORAL  1: streaming (non-temporal) loads of the
- *                         populations in the sweep (default 1, except 0 for
- *                         LBM_F64); stores are always plain.  Results are
- *                         identical.
+ *                         populations in the sweep; stores are always plain.
+ *                         Default 1 when the context's two population buffers
+ *                         hold at most 768 MiB in all and the storage is not
+ *                         LBM_F64, else 0.  Results are identical.
  *   LBM_TUNE_COOP_REMAP   1 (default): when every workgroup of the coupling
  *                         launch can be resident at once (up to the device's
  *                         occupancy for it: a few boxes per launch), all

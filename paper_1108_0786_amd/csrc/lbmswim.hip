@@ -199,10 +199,6 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     if (!params || nbox < 1 || nbox > 65535) return LBM_E_ARG;
     lbm_ctx *c = new lbm_ctx();
     c->storage = params[0].storage;
-    // non-temporal loads pay off for every format but FP64 (sweep of the
-    // 256x128x128 box: FP32 129 -> 119 us, FP16S and BF16S 81-88 -> 65 us,
-    // FP64 242 -> 247 us); non-temporal stores were slower for every format
-    c->nontemporal = c->storage == LBM_F64 ? 0 : 1;
     c->stream = (hipStream_t)params[0].stream;
     for (int b = 0; b < nbox; ++b) {
         int rc = validate_params(c, params[b]);
@@ -236,6 +232,16 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
             *out = c;
             return fail(c, LBM_E_HIP, "clearing flags failed");
         }
+    }
+    // Non-temporal population loads in the sweep, measured on boxes of 2 to
+    // 34 million cells: they pay while the two population buffers of the
+    // context hold at most about 768 MiB (FP32 sweep up to 14% faster,
+    // FP16S/BF16S 25-29%) and cost 5-12% beyond that; FP64 gains nothing
+    // at any size.  Non-temporal stores were slower in every case.
+    {
+        double state = 0.0;
+        for (const HostBox &h : c->boxes) state += 2.0 * 19.0 * (double)h.stride * (double)storage_bytes(c->storage);
+        c->nontemporal = c->storage != LBM_F64 && state <= 768.0 * 1024.0 * 1024.0 ? 1 : 0;
     }
     *out = c;
     HIP_TRY(c, hipMalloc(&c->d_boxes, sizeof(BoxDesc) * nbox));
