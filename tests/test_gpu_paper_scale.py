@@ -29,6 +29,7 @@ import dataclasses
 import json
 import math
 import os
+import time
 
 import numpy as np
 import pytest
@@ -97,7 +98,9 @@ def batch():
     cases = [W.paper_design(d, "f32") for d in DESIGNS]
     T = W.PAPER_SI["period"]
     print(f"[gpu] design study: {len(cases)} swimmers, 200x100x100 each, {5 * T} steps FP32", flush=True)
-    state = dict(sim=BatchSim(cases, storage="f32", traj_cap=T + 1), cases=cases, T=T, periods=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    state = dict(sim=BatchSim(cases, storage="f32", traj_cap=T + 1), cases=cases, T=T, periods=0, t0=t0)
     yield state
     state["sim"].close()
 
@@ -106,6 +109,13 @@ def _advance(batch):
     batch["sim"].step(batch["T"])
     batch["sim"].status()
     batch["periods"] += 1
+    if batch["periods"] == 5:
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - batch["t0"]
+        c = batch["cases"][0]
+        updates = len(batch["cases"]) * c.nx * c.ny * c.nz * 5 * batch["T"]
+        print(f"[gpu] design study: {sec:.1f} s for five periods, set-up included "
+              f"({sec / (5 * batch['T']) * 1e3:.3f} ms per batched step, {updates / sec / 1e9:.1f} GLUPS)", flush=True)
     print(f"[gpu] design study: period {batch['periods']} done", flush=True)
 
 
