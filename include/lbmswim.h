@@ -262,7 +262,10 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
 
 /* Launch tuning of a context (values outside the listed ones give LBM_E_ARG):
  *   LBM_TUNE_BLOCK        sweep workgroup size: 128, 256 (default) or 512
- *   LBM_TUNE_XCD_ORDER    1: give each XCD a contiguous slab of tiles (default 0)
+ *   LBM_TUNE_XCD_ORDER    1: give each XCD a contiguous slab of tiles; 0: hand
+ *                         out tiles in order.  Default 1 when the context's
+ *                         two population buffers hold more than 2 GiB in all,
+ *                         else 0.  Results are identical.
  *   LBM_TUNE_GRAPH_STEPS  0: launch every kernel; n > 0 (default 32): replay a
  *                         captured HIP graph of n steps where possible
  *   LBM_TUNE_FULL_REMAP   1: map the bodies every step even when no cell can

@@ -238,10 +238,15 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     // context hold at most about 768 MiB (FP32 sweep up to 14% faster,
     // FP16S/BF16S 25-29%) and cost 5-12% beyond that; FP64 gains nothing
     // at any size.  Non-temporal stores were slower in every case.
+    // The XCD-aware tile order (one contiguous slab of tiles per XCD) pays on
+    // states of 2.5 GB and more (5-11% on 5.1-5.2 GB of FP32, 2.5-2.6 GB of
+    // FP16S) and costs 2-16% on states of 1 GB and less, so it is on above
+    // 2 GiB.
     {
         double state = 0.0;
         for (const HostBox &h : c->boxes) state += 2.0 * 19.0 * (double)h.stride * (double)storage_bytes(c->storage);
         c->nontemporal = c->storage != LBM_F64 && state <= 768.0 * 1024.0 * 1024.0 ? 1 : 0;
+        c->xcd_order = state > 2048.0 * 1024.0 * 1024.0 ? 1 : 0;
     }
     *out = c;
     HIP_TRY(c, hipMalloc(&c->d_boxes, sizeof(BoxDesc) * nbox));

@@ -185,7 +185,8 @@ def test_overlapping_bodies_rejected():
 
 
 @pytest.mark.parametrize("tune", [{"graph_steps": 0}, {"graph_steps": 7}, {"block": 128, "xcd_order": 0},
-                                  {"block": 512}, {"full_remap": 1}, {"nontemporal": 1}, {"coop_remap": 0}])
+                                  {"xcd_order": 1}, {"block": 512}, {"full_remap": 1}, {"nontemporal": 1},
+                                  {"coop_remap": 0}])
 def test_launch_options_are_bitwise_identical(tune):
     # graphs, tile sizes, tile order, the remap skip and the mapping by one or
     # by all of a box's workgroups change nothing: the reductions are in fixed
