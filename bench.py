@@ -195,6 +195,44 @@ def copy_ceiling(nbytes=2 << 30, reps=20):
     return best
 
 
+def pattern_ceiling(n, stride, elem_bytes, reps=20):
+    """Practical ceiling of the sweep's access pattern at this box size: the
+    best of plain and non-temporal loads for ``lbm_stream_copy`` (19 streams
+    of ``n`` elements in, 19 out, the sweep's stride), read + write counted,
+    timed with torch events on the stream it runs on."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1108_0786_amd import _abi
+
+    lib = _abi.load()
+    nbytes = 19 * stride * elem_bytes
+    src = torch.ones(nbytes // 2, dtype=torch.int16, device="cuda:0")
+    dst = torch.zeros_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    best = 0.0
+    for nt in (0, 1):
+        def run():
+            rc = lib.lbm_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n, stride,
+                                     elem_bytes, nt, C.c_void_p(stream))
+            assert rc == 0
+        for _ in range(3):
+            run()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        gbs = 2 * 19 * n * elem_bytes / (a.elapsed_time(b) / reps / 1e3) / 1e9
+        print(f"[bench] sweep-pattern copy, {elem_bytes}-byte elements, nontemporal loads={nt}: {gbs:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        best = max(best, gbs)
+    del src, dst
+    return best
+
+
 def cpu_baseline(case, steps=3):
     """The oracle as it stands, on a few steps of the same box (single core:
     NumPy elementwise kernels)."""
@@ -237,6 +275,10 @@ def main():
     case = W.plain_at_scale(storage="f32")
     copy_gbs = copy_ceiling()
     print(f"[bench] plain copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    from paper_1108_0786_amd.sim import padded_stride
+    for st, r in results.items():
+        r["pattern_gbs"] = pattern_ceiling(case.ncells, padded_stride(case.ncells), STORAGE_BYTES[st])
+        r["frac_of_pattern"] = r["sweep_gbs"] / r["pattern_gbs"]
     batched = None if args.no_batch else batched_leg(args.batch_periods)
     cpu = None if args.no_cpu else cpu_baseline(W.plain_at_scale(storage="f64"))
     line = {
@@ -259,7 +301,9 @@ def main():
                      "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "sweep_kernel<float>", "bytes_per_launch": head["sweep_bytes"],
                      "launch_us": round(head["sweep_us"], 2), "copy_ceiling_gbs": round(copy_gbs, 1),
-                     "frac_of_copy": round(head["sweep_gbs"] / copy_gbs, 4)},
+                     "frac_of_copy": round(head["sweep_gbs"] / copy_gbs, 4),
+                     "pattern_ceiling_gbs": round(head["pattern_gbs"], 1),
+                     "frac_of_pattern": round(head["frac_of_pattern"], 4)},
         "cpu_baseline": cpu,
         "batched_sweep": batched,
         "legs": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}

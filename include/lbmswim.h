@@ -326,6 +326,18 @@ int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs
 int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_per_cu, int32_t nontemporal,
                     void *stream);
 
+/* Measurement aid, not part of the method: the sweep's memory access
+ * pattern without its arithmetic, as the practical ceiling of that pattern
+ * at a given box size.  Copies 19 streams of n elements of elem_bytes bytes
+ * each (2, 4 or 8), stream a starting at element a * stride, from src to dst
+ * (device memory, each at least 19 * stride elements, not overlapping), on
+ * `stream` (hipStream_t): one element per thread, its 19 loads issued before
+ * its 19 stores, non-temporal loads if `nontemporal`, plain stores.
+ * LBM_E_ARG for a null pointer, n <= 0, stride < n, another element size or
+ * sizes whose offsets overflow; LBM_E_HIP when the launch fails. */
+int lbm_stream_copy(const void *src, void *dst, int64_t n, int64_t stride, int32_t elem_bytes, int32_t nontemporal,
+                    void *stream);
+
 /* Write sizeof(lbm_params), sizeof(lbm_body), sizeof(lbm_spring) and
  * sizeof(lbm_drive) into out[0..3] so that a binding can check its struct
  * layout.  Touches no device. */

@@ -650,6 +650,33 @@ __global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src
     for (; i < n; i += stride) st<NT>(dst + i, ld<NT>(src + i));
 }
 
+// The sweep's memory access pattern without its arithmetic: 19 streams of n
+// elements, stream a at element offset a * stride, one element per thread,
+// the 19 loads issued before the 19 stores.
+template <typename T, bool NT>
+__global__ __launch_bounds__(256) void stream_copy_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                          size_t n, size_t stride) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+        v[a] = NT ? __builtin_nontemporal_load(src + (size_t)a * stride + i) : src[(size_t)a * stride + i];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) dst[(size_t)a * stride + i] = v[a];
+}
+
+template <typename T>
+void launch_stream_copy(const void *src, void *dst, size_t n, size_t stride, bool nt, hipStream_t stream) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (nt)
+        hipLaunchKernelGGL((stream_copy_kernel<T, true>), dim3(blocks), dim3(256), 0, stream, (const T *)src,
+                           (T *)dst, n, stride);
+    else
+        hipLaunchKernelGGL((stream_copy_kernel<T, false>), dim3(blocks), dim3(256), 0, stream, (const T *)src,
+                           (T *)dst, n, stride);
+}
+
 __global__ void save_hist_kernel(const BoxDesc *boxes, BodyHist *out) {
     const BoxDesc &B = boxes[0];
     const int b = threadIdx.x;
@@ -933,6 +960,19 @@ int lbm_copy_kernel(const void *src, void *dst, int64_t bytes, int32_t blocks_pe
     else
         hipLaunchKernelGGL(copy_kernel<false>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const u32x4 *)src,
                            (u32x4 *)dst, n);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int lbm_stream_copy(const void *src, void *dst, int64_t n, int64_t stride, int32_t elem_bytes, int32_t nontemporal,
+                    void *stream) {
+    if (!src || !dst || n <= 0 || stride < n || (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
+        return LBM_E_ARG;
+    // the grid and the largest element offset must fit their types
+    if ((n + 255) / 256 > 0x7fffffffLL || stride > (INT64_MAX / 19) / 8) return LBM_E_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    if (elem_bytes == 2) launch_stream_copy<uint16_t>(src, dst, (size_t)n, (size_t)stride, nontemporal != 0, s);
+    else if (elem_bytes == 4) launch_stream_copy<uint32_t>(src, dst, (size_t)n, (size_t)stride, nontemporal != 0, s);
+    else launch_stream_copy<uint64_t>(src, dst, (size_t)n, (size_t)stride, nontemporal != 0, s);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 

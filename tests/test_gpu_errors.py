@@ -158,3 +158,33 @@ def test_relaxation_time_extremes(tau):
     err = _parity(case, 80, df0)
     print(f"[gpu] tau {tau}: dF error {err:.1e}", flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("elem_bytes", [2, 4, 8])
+def test_measurement_copies_move_exactly_their_bytes(elem_bytes):
+    # the two copy kernels behind the bandwidth ceilings: every byte they are
+    # asked to move arrives, and nothing else is written
+    abi, lib = _lib()
+    n, stride = 1000, 1088
+    print(f"[gpu] stream copy of {elem_bytes}-byte elements", flush=True)
+    g = torch.Generator(device="cpu").manual_seed(elem_bytes)
+    src = torch.randint(-30000, 30000, (19 * stride * elem_bytes // 2,), dtype=torch.int16, generator=g).cuda()
+    for nt in (0, 1):
+        dst = torch.zeros_like(src)
+        stream = torch.cuda.current_stream().cuda_stream
+        assert lib.lbm_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n, stride, elem_bytes,
+                                   nt, C.c_void_p(stream)) == abi.LBM_OK
+        torch.cuda.synchronize()
+        s = src.view(19, stride * elem_bytes // 2).cpu()
+        d = dst.view(19, stride * elem_bytes // 2).cpu()
+        k = n * elem_bytes // 2
+        assert torch.equal(d[:, :k], s[:, :k])
+        assert not d[:, k:].any()
+        dst = torch.zeros_like(src)
+        nbytes = 1024 * 16                     # within the smallest buffer (19 * 1088 * 2 bytes)
+        assert nbytes <= src.numel() * 2
+        assert lib.lbm_copy_kernel(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, 0, nt,
+                                   C.c_void_p(stream)) == abi.LBM_OK
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:nbytes // 2].cpu(), src[:nbytes // 2].cpu())
+        assert not dst[nbytes // 2:].any()
