@@ -13,8 +13,10 @@ over the whole box, / 1e6) of the FP32 leg; ``roofline`` divides the
 sweep kernel's algorithmic bytes per launch by its mean launch time taken
 from HIP events recorded on the library's stream around every sweep of a
 second pass of the same number of steps (launched one by one, since the
-events cannot sit inside the replayed graphs); ``cpu_baseline`` times the CPU oracle on a few steps of the
-same box."""
+events cannot sit inside the replayed graphs), and sets that rate beside
+two measured ceilings: a plain streaming copy and a copy with the sweep's
+own access pattern (``lbm_stream_copy``); ``cpu_baseline`` times the CPU
+oracle on a few steps of the same box."""
 from __future__ import annotations
 
 import argparse
