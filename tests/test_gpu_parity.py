@@ -205,6 +205,30 @@ def test_launch_options_are_bitwise_identical(tune):
     other.close()
 
 
+@pytest.mark.parametrize("tune", [{"xcd_order": 1}, {"xcd_order": 1, "block": 128}, {"xcd_order": 1, "block": 512}])
+def test_tile_order_on_a_ragged_grid(tune):
+    # 45x31x32 cells: 175 tiles of 256 (349 of 128), not a multiple of the 8
+    # XCDs, and a partial last tile; the XCD-aware order must still sweep
+    # every tile exactly once
+    b, s, d = W.swimmer((22.0, 15.0, 16.0), r=3.0, l0=(10.0, 10.0), k=0.05, gamma=0.01,
+                        amplitude=2e-4, period=200.0, phase_lag=math.pi / 2)
+    case = W.Case("ragged_45x31x32", 45, 31, 32, 1.0, bodies=b, springs=s, drives=[d], steps=60)
+    df0 = W.initial_populations(case, seed=11, amp=1e-4)
+    print(f"[gpu] ragged grid {tune}", flush=True)
+    orc = OracleSim(case, df0=df0).run(60)
+    ref = _sim(case, storage="f64", traj_cap=60, df0=df0)
+    ref.step(60)
+    other = _sim(case, storage="f64", traj_cap=60, df0=df0, tune=tune)
+    other.step(60)
+    err = np.abs(ref.populations() - orc.populations()).max() / np.abs(orc.populations()).max()
+    assert err < 1e-12
+    assert np.array_equal(ref.populations(), other.populations())
+    assert np.array_equal(ref.trajectory(), other.trajectory())
+    assert np.array_equal(ref.flags(), other.flags())
+    ref.close()
+    other.close()
+
+
 def _averaged_case(steps=300):
     # tau 0.6: the plain explicit coupling lets a period-2 mode grow here
     b, s, d = W.swimmer((16.0, 12.0, 12.0), r=3.0, l0=(10.0, 10.0), k=0.05, gamma=0.01,
