@@ -254,7 +254,8 @@ int lbm_status(lbm_ctx *ctx);
  * pass (scratch: nsteps/checkpoint_every + checkpoint_every + 1 population
  * states, two adjoint fields in double, owned by the context).  The mapping
  * must not change during the run (the flags are held fixed in the reverse
- * pass): LBM_E_STATE otherwise.  Capsule orientation is treated as a constant
+ * pass): LBM_E_STATE if any cell changed its owner at any step of the run,
+ * even if it changed back before the end.  Capsule orientation is treated as a constant
  * in the reverse pass.  Afterwards the context is in the same state as after
  * lbm_step(ctx, nsteps).  Synchronising. */
 int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const double *dJ_ddisp,

@@ -45,6 +45,15 @@ def _store(table):
     os.replace(tmp, path)
 
 
+def timed_steps(steps, graph_steps):
+    """Steps of a candidate's timing run: ``steps`` rounded up to a whole,
+    non-zero number of its graphs (lbm_step replays a graph only for runs of
+    at least ``graph_steps`` steps, and launches the remainder one by one)."""
+    if graph_steps <= 0:
+        return max(steps, 1)
+    return graph_steps * max(1, -(-steps // graph_steps))
+
+
 def tune(sim, steps=64, use_cache=True, verbose=False):
     """Pick and apply the fastest candidate for ``sim`` (a Sim or BatchSim).
 
@@ -64,12 +73,16 @@ def tune(sim, steps=64, use_cache=True, verbose=False):
     for cand in CANDIDATES:
         for k, v in cand.items():
             sim.tune(k, v)
-        sim.step(cand["graph_steps"])  # capture and warm up
+        g = cand["graph_steps"]
+        sim.step(g)  # capture and warm up
         torch.cuda.synchronize()
+        # a whole number of graphs, at least one: a shorter run would launch
+        # every kernel itself and time another launch sequence
+        n = timed_steps(steps, g)
         t0 = time.perf_counter()
-        sim.step(steps)
+        sim.step(n)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / n
         results.append((dt, cand))
         if verbose:
             print(f"[autotune] {key} {cand}: {dt * 1e6:.1f} us/step", flush=True)

@@ -40,6 +40,7 @@ struct CoupleCtl {
     int lo[3], hi[3];            // ... and the cell box to map
     int counts[kRedBlocks];      // links found in each workgroup's slice of the cell box
     unsigned long long margin[kMaxBodies];  // bits of each body's margin (a non-negative double)
+    unsigned owner_changes;      // cells whose owner a mapping has changed, counted since set-up
 };
 
 // partial momentum-exchange sums of one body over one slice of the links:
@@ -507,6 +508,7 @@ __device__ void map_owners(const BoxDesc &B, const CoupleShared &sh, const MapBo
         }
         B.old_owner[c] = old;
         B.flags[c] = (uint8_t)owner;
+        if (old != owner) atomicAdd(&((CoupleCtl *)B.ctl)->owner_changes, 1u);
     }
 }
 

@@ -115,6 +115,16 @@ int fail(lbm_ctx *c, int code, const std::string &msg) {
 
 size_t storage_bytes(int s) { return s == LBM_F64 ? 8 : (s == LBM_F32 ? 4 : 2); }
 
+// A copy ordered after all work queued on the context's stream, waited for
+// before returning (a plain hipMemcpy would run on the null stream, which a
+// non-blocking stream does not wait for).
+int copy_sync(lbm_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+    if (bytes == 0) return LBM_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 int validate_params(lbm_ctx *c, const lbm_params &p) {
     if (p.nx < 3 || p.ny < 3 || p.nz < 3) return fail(c, LBM_E_ARG, "box must be at least 3 cells per axis");
     if ((double)p.nx * p.ny * p.nz > 2.0e9) return fail(c, LBM_E_ARG, "box exceeds 2e9 cells");
@@ -748,8 +758,10 @@ int adjoint_impl(lbm_ctx *c, int64_t nsteps, int ce, const double *w_host, doubl
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const long long step0 = d0.step;
     const int cur0 = d0.cur;
-    std::vector<uint8_t> flags0(h.N), flags1(h.N);
-    HIP_TRY(c, hipMemcpy(flags0.data(), h.p.flags, h.N, hipMemcpyDeviceToHost));
+    // owner changes made by the mappings so far; any during the forward run
+    // (even a cell covered and uncovered again) breaks the fixed-flag reverse pass
+    unsigned changes0 = 0, changes1 = 0;
+    if ((rc = copy_sync(c, &changes0, &h.ctl->owner_changes, sizeof(unsigned), hipMemcpyDeviceToHost))) return rc;
     auto pop = [&](int cur) { return cur ? h.p.pop[1] : h.p.pop[0]; };
     auto ckpt = [&](int64_t k) { return (char *)c->adj_ckpt + (size_t)k * state_bytes; };
     auto seg = [&](int64_t m) { return (char *)c->adj_seg + (size_t)m * state_bytes; };
@@ -771,14 +783,14 @@ int adjoint_impl(lbm_ctx *c, int64_t nsteps, int ce, const double *w_host, doubl
     HIP_TRY(c, hipMemcpyAsync(ckpt(K), pop(cur_end), state_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->adj_ckpt_bodies + K * kMaxBodies, h.d_bodies, body_bytes, hipMemcpyDeviceToDevice,
                               c->stream));
-    HIP_TRY(c, hipMemcpy(flags1.data(), h.p.flags, h.N, hipMemcpyDeviceToHost));
-    for (int i = 0; i < h.N; ++i)
-        if ((flags0[i] & kOwnerMask) != (flags1[i] & kOwnerMask))
-            return fail(c, LBM_E_STATE, "the mapping changed during the run; the adjoint holds the flags fixed");
+    if ((rc = copy_sync(c, &changes1, &h.ctl->owner_changes, sizeof(unsigned), hipMemcpyDeviceToHost))) return rc;
+    if (changes1 != changes0)
+        return fail(c, LBM_E_STATE, "the mapping changed during the run; the adjoint holds the flags fixed");
     // objective
     std::vector<BodyHist> fin(nb);
-    HIP_TRY(c, hipMemcpy(fin.data(), c->adj_hist + (size_t)nsteps * nb, sizeof(BodyHist) * nb,
-                         hipMemcpyDeviceToHost));
+    if ((rc = copy_sync(c, fin.data(), c->adj_hist + (size_t)nsteps * nb, sizeof(BodyHist) * nb,
+                        hipMemcpyDeviceToHost)))
+        return rc;
     double Jv = 0.0;
     for (int b = 0; b < nb; ++b)
         for (int q = 0; q < 3; ++q) Jv += w_host[3 * b + q] * fin[b].D[q];
@@ -786,7 +798,7 @@ int adjoint_impl(lbm_ctx *c, int64_t nsteps, int ce, const double *w_host, doubl
     // reverse pass
     double *wdev = nullptr;
     HIP_TRY(c, hipMalloc(&wdev, sizeof(double) * 3 * nb));
-    HIP_TRY(c, hipMemcpy(wdev, w_host, sizeof(double) * 3 * nb, hipMemcpyHostToDevice));
+    if ((rc = copy_sync(c, wdev, w_host, sizeof(double) * 3 * nb, hipMemcpyHostToDevice))) return rc;
     hipLaunchKernelGGL(init_adjoint_kernel, dim3(1), dim3(64), 0, c->stream, c->adj_body, wdev, nb, c->adj_grad);
     HIP_TRY(c, hipMemsetAsync(c->adj_lam[0], 0, c->adj_lam_bytes, c->stream));
     int lcur = 0;  // adj_lam[lcur] holds the adjoint of the populations after the step being reversed
@@ -992,8 +1004,10 @@ int lbm_set_bodies_box(lbm_ctx *c, int32_t box, const lbm_body *bodies, int32_t 
     // bodies already on the lattice: keep their last mapped positions so that the
     // remap covers both the old and the new cells
     std::vector<DevBody> old(h.bodies.size());
-    if (h.mapped && !h.bodies.empty())
-        HIP_TRY(c, hipMemcpy(old.data(), h.d_bodies, sizeof(DevBody) * old.size(), hipMemcpyDeviceToHost));
+    if (h.mapped && !h.bodies.empty()) {
+        rc = copy_sync(c, old.data(), h.d_bodies, sizeof(DevBody) * old.size(), hipMemcpyDeviceToHost);
+        if (rc) return rc;
+    }
     h.bodies.assign(bodies, bodies + nb);
     h.springs.assign(springs, springs + ns);
     h.drives.assign(drives, drives + nd);
@@ -1162,10 +1176,9 @@ int lbm_get_links(lbm_ctx *c, int32_t box, int32_t *cell, int8_t *dir, int8_t *b
     if (d.link_count > cap) return fail(c, LBM_E_CAPACITY, "output capacity too small");
     if (d.link_count == 0) return LBM_OK;
     if (!cell || !dir || !body) return fail(c, LBM_E_ARG, "null output");
-    HIP_TRY(c, hipMemcpy(cell, h.link_cell, sizeof(int) * d.link_count, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(dir, h.link_dir, d.link_count, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(body, h.link_body, d.link_count, hipMemcpyDeviceToHost));
-    return LBM_OK;
+    HIP_TRY(c, hipMemcpyAsync(cell, h.link_cell, sizeof(int) * d.link_count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dir, h.link_dir, d.link_count, hipMemcpyDeviceToHost, c->stream));
+    return copy_sync(c, body, h.link_body, d.link_count, hipMemcpyDeviceToHost);
 }
 
 int lbm_export_populations(lbm_ctx *c, int32_t box, double *dst) {

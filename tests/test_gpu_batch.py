@@ -1,6 +1,8 @@
-"""Batched boxes (one context, one launch per kernel per step for all boxes)
-against sequential single-box runs: bitwise identical per box, including
-boxes that stop early at their step limit."""
+"""Batched boxes (one context, one launch per kernel per step for all boxes):
+against sequential single-box runs (bitwise identical per box, including
+boxes that stop early at their step limit) and against the CPU oracle, box
+by box, on boxes of the parameter sweep with different sizes, relaxation
+times and coupling forms."""
 import numpy as np
 import pytest
 
@@ -56,3 +58,44 @@ def test_autotuner_picks_a_candidate_and_keeps_results(tmp_path, monkeypatch):
         assert np.array_equal(ref.populations(b), tuned.populations(b))
     ref.close()
     tuned.close()
+
+
+# boxes of the seed-7 sweep: two at tau < 0.65 (two-step force mean), three
+# at tau = 0.73, 0.93 and 1.19 (plain coupling of Alg. 2), three box shapes
+ORACLE_BOXES = (6, 37, 50, 9, 65)
+
+
+@pytest.fixture(scope="module")
+def sweep_oracle():
+    from oracle_jobs import run_many
+    cases = W.batched_sweep(seed=7)
+    picked = [cases[i] for i in ORACLE_BOXES]
+    steps = [150, 150, 150, 150, 120]
+    print("[gpu] oracle runs of " + ", ".join(f"{c.name} (tau {c.tau:.3f}, force mean {c.force_average})"
+                                            for c in picked), flush=True)
+    return picked, steps, run_many(list(zip(picked, steps)), workers=5)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_batched_boxes_against_oracle(sweep_oracle, storage, tol):
+    from paper_1108_0786_amd.sim import BatchSim
+    cases, steps, gold = sweep_oracle
+    assert any(c.force_average for c in cases) and any(not c.force_average for c in cases)
+    print(f"[gpu] batch of {len(cases)} against the oracle ({storage})", flush=True)
+    batch = BatchSim(cases, storage=storage, traj_cap=max(steps))
+    for b, s in enumerate(steps):
+        batch.set_step_limit(b, s)
+    batch.step(max(steps))
+    batch.status()
+    for b, (c, s, (F, T, D, V, df, flags)) in enumerate(zip(cases, steps, gold)):
+        assert batch.step_count(b) == s
+        tr = batch.trajectory(b)[:s]
+        eF = np.abs(tr[:, :, 9:12] - F).max() / np.abs(F).max()
+        eD = np.abs(tr[:, :, 0] - D[:, :, 0]).max() / np.abs(D[:, :, 0]).max()
+        eV = np.abs(tr[:, :, 3] - V[:, :, 0]).max() / np.abs(V[:, :, 0]).max()
+        pg = batch.populations(b)
+        eP = np.abs(pg - df).max() / np.abs(df).max()
+        print(f"[gpu] {c.name} {storage}: F {eF:.2e} D {eD:.2e} V {eV:.2e} dF {eP:.2e}", flush=True)
+        assert np.array_equal(batch.flags(b) & 0x7F, flags), c.name
+        assert eF < tol and eD < tol and eV < tol and eP < tol, c.name
+    batch.close()

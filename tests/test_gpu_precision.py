@@ -3,7 +3,7 @@ with FP64, FP32, shifted-FP16 and shifted-BF16 population storage, against
 the FP64 oracle's trajectory (stored by tests/golden/make_goldens.py, which
 calls only the oracle).  The error of each storage type is printed; FP64 and
 FP32 are held to the parity bars, the 16-bit formats to the bound their
-rounding allows."""
+rounding allows, populations included."""
 import os
 
 import numpy as np
@@ -53,9 +53,17 @@ def test_capsule_crop_against_oracle(design, storage):
     assert np.array_equal(sim.flags()[gold["cells"]] & 0x7F, gold["flags"])
     b = BOUND[storage]
     assert eF < b and eD < b and eC < b
-    # the velocity is the difference of consecutive centroid positions, so its
-    # error bound is twice the displacement bound on the scale max|D| / max|v|
-    assert eV < 2.0 * b * max(1.0, dscale / np.abs(vo).max())
+    if storage == "f32":
+        # the FP32 parity bar holds for the centroid velocity and the
+        # populations themselves
+        assert eV < b and eP < b
+    else:
+        # the velocity is the difference of consecutive centroid positions,
+        # so its error carries the factor max|D| / max|v| (about 1e3 here)
+        # over the displacement error: in FP64 this cancellation alone
+        # reaches 1e-12, and the 16-bit formats store coarser populations
+        assert eV < 2.0 * b * max(1.0, dscale / np.abs(vo).max())
+        assert eP < b
     sim.close()
 
 

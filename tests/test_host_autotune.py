@@ -76,3 +76,34 @@ def test_fastest_candidate_is_chosen_and_cached(tmp_path, monkeypatch):
     tried = {tuple(sorted(c.items())) for c in autotune.CANDIDATES}
     assert len(tried) == len(autotune.CANDIDATES)
     assert sum(1 for k, _ in sim.calls if k == "block") == len(autotune.CANDIDATES) + 1
+
+
+class RecordingSim(FakeSim):
+    """Records the graph length in force at every step call."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.runs = []
+
+    def step(self, n):
+        self.runs.append((self.current.get("graph_steps"), n))
+
+
+def test_timed_steps_cover_whole_graphs():
+    assert autotune.timed_steps(32, 64) == 64
+    assert autotune.timed_steps(32, 16) == 32
+    assert autotune.timed_steps(40, 16) == 48
+    assert autotune.timed_steps(5, 0) == 5
+
+
+def test_graph_candidates_are_timed_with_their_graphs(tmp_path, monkeypatch):
+    # every timing run of a candidate is a whole, non-zero number of its
+    # graphs, so that lbm_step replays the captured graph it would use
+    monkeypatch.setenv("LBMSWIM_TUNING_CACHE", str(tmp_path / "tuning.json"))
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    sim = RecordingSim([(96, 48, 48)])
+    autotune.tune(sim, steps=32)
+    timed = sim.runs[1::2]          # each candidate: warm-up run, then timed run
+    assert len(timed) == len(autotune.CANDIDATES)
+    for g, n in timed:
+        assert g > 0 and n >= g and n % g == 0, (g, n)
