@@ -67,6 +67,8 @@ def time_leg(case, storage, steps, warmup):
     sim = Sim(case, storage=storage, device="cuda:0", shift_log2=16)
     n_fluid = int((sim.flags() & 0x7F == 0).sum())
     sim.step(warmup)
+    # capture the graphs the timed run replays (nothing runs)
+    sim.prepare(steps)
     torch.cuda.synchronize()
     # throughput: steps replayed from HIP graphs, nothing recorded in between
     t0 = time.perf_counter()
@@ -131,6 +133,7 @@ def batched_leg(periods=10):
     batch = BatchSim(cases, storage="f32", tune=best)
     for b, c in enumerate(cases):
         batch.set_step_limit(b, c.steps)
+    batch.prepare(max(c.steps for c in cases))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.step(max(c.steps for c in cases))
@@ -145,6 +148,7 @@ def batched_leg(periods=10):
     t_seq = 0.0
     for i, c in enumerate(cases):
         sim = Sim(c, storage="f32")
+        sim.prepare(c.steps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(c.steps)
@@ -158,6 +162,53 @@ def batched_leg(periods=10):
             "sequential_s": round(t_seq, 3), "batched_mlups": round(lups / t_batch / 1e6, 1),
             "sequential_mlups": round(lups / t_seq / 1e6, 1), "speedup": round(t_seq / t_batch, 3),
             "tuning": best, "bitwise_equal_middle_body_displacement": True}
+
+
+def adjoint_leg(steps=1000, every=50):
+    """The hand-written reverse pass on the 128x64x64 adjoint workload (FP64,
+    tau 0.9, r = 4 swimmer, two periods of 500 steps): wall time of
+    ``lbm_adjoint`` over ``steps`` steps with checkpoints every ``every``,
+    beside the same number of forward steps replayed from graphs.  The
+    reverse pass runs every step forward twice (once to take checkpoints,
+    once per segment to rebuild its states) and one adjoint sweep
+    (``adjoint_sweep_kernel``) per step."""
+    import torch
+
+    import workloads as W
+    from paper_1108_0786_amd.sim import Sim
+
+    case = W.adjoint_case(storage="f64", periods=steps // 500)
+    print(f"[bench] adjoint: {case.name}, {steps} steps, checkpoints every {every}", file=sys.stderr, flush=True)
+    fwd = Sim(case, storage="f64", device="cuda:0")
+    n_fluid = int((fwd.flags() & 0x7F == 0).sum())
+    fwd.prepare(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    fwd.close()
+    adj = Sim(case, storage="f64", device="cuda:0")
+    adj.adjoint(steps // 10, every)          # first call: scratch allocation and kernel loading
+    adj.close()
+    adj = Sim(case, storage="f64", device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, grad = adj.adjoint(steps, every)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    adj.close()
+    # adjoint sweep per fluid cell: the forward deviations (19 doubles) and
+    # the adjoint of the next step (19 doubles) in, the adjoint out (19
+    # doubles), and the flag byte
+    per_cell = 19 * 8 * 3 + 1
+    out = {"workload": f"{case.nx}x{case.ny}x{case.nz} FP64 swimmer, tau {case.tau}", "steps": steps,
+           "checkpoint_every": every, "forward_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
+           "ratio": round(t_adj / t_fwd, 2), "adjoint_sweep_bytes_per_fluid_cell": per_cell,
+           "fluid_cells": n_fluid, "J": J, "grad": [float(g) for g in grad]}
+    print(f"[bench] adjoint: forward {t_fwd * 1e3:.1f} ms, adjoint {t_adj * 1e3:.1f} ms "
+          f"({t_adj / t_fwd:.1f}x)", file=sys.stderr, flush=True)
+    return out
 
 
 def copy_ceiling(nbytes=2 << 30, reps=20):
@@ -235,19 +286,50 @@ def pattern_ceiling(n, stride, elem_bytes, reps=20):
     return best
 
 
-def cpu_baseline(case, steps=3):
-    """The oracle as it stands, on a few steps of the same box (single core:
-    NumPy elementwise kernels)."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def time_oracle(case, steps):
     from oracle import OracleSim
 
-    print(f"[bench] cpu baseline: oracle, {steps} steps of {case.name}", file=sys.stderr, flush=True)
     sim = OracleSim(case)
     t0 = time.perf_counter()
     sim.run(steps)
-    t1 = time.perf_counter()
-    return {"value": case.ncells * steps / (t1 - t0) / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} coupled steps of the {case.nx}x{case.ny}x{case.nz} FP64 case on one host core"
-                      f" ({platform.processor() or platform.machine()}, {os.cpu_count()} cpus visible)"}
+    return case.ncells * steps / (time.perf_counter() - t0) / 1e6
+
+
+def cpu_baseline(case, steps=8):
+    """The oracle as it stands, on a bounded sample of the same box: NumPy
+    elementwise kernels, one host core (no BLAS calls on this path)."""
+    print(f"[bench] cpu baseline: oracle, {steps} steps of {case.name}", file=sys.stderr, flush=True)
+    mlups = time_oracle(case, steps)
+    return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} coupled steps of the {case.nx}x{case.ny}x{case.nz} FP64 case on one host core",
+            "cpu": cpu_model(), "cpus_visible": os.cpu_count()}
+
+
+def cpu_configs():
+    """The oracle on the other workloads (``--cpu-configs``): the 48x32x32
+    case in full (400 steps), and 100-step samples of the 128x64x64 capsule
+    crop and of the 128x64x64 adjoint workload, one host core each."""
+    import workloads as W
+
+    out = {}
+    for name, case, steps in (("48x32x32, 400 steps", W.plain_f64_small(), 400),
+                              ("capsule crop 128x64x64 S-C-S, 100 of 1000 steps", W.capsule_crop("SCS", "f64"), 100),
+                              ("adjoint workload 128x64x64, 100 of 1000 steps", W.adjoint_case(storage="f64"), 100)):
+        print(f"[bench] cpu: oracle, {name}", file=sys.stderr, flush=True)
+        out[name] = round(time_oracle(case, steps), 3)
+    return out
 
 
 def main():
@@ -259,6 +341,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-periods", type=int, default=10)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the reverse pass on the 128x64x64 adjoint workload")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on the other workloads (several minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the swimmer step runs and is timed on a single "
@@ -282,7 +368,10 @@ def main():
         r["pattern_gbs"] = pattern_ceiling(case.ncells, padded_stride(case.ncells), STORAGE_BYTES[st])
         r["frac_of_pattern"] = r["sweep_gbs"] / r["pattern_gbs"]
     batched = None if args.no_batch else batched_leg(args.batch_periods)
+    adjoint = adjoint_leg() if args.adjoint else None
     cpu = None if args.no_cpu else cpu_baseline(W.plain_at_scale(storage="f64"))
+    if cpu is not None and args.cpu_configs:
+        cpu["other_workloads_mlups"] = cpu_configs()
     line = {
         "metric": "MLUPS & % HBM roofline, fused D3Q19+moving-bead step, FP32 vs FP64/FP16, 1 GPU",
         "value": round(head["mlups"], 1),
@@ -308,6 +397,7 @@ def main():
                      "frac_of_pattern": round(head["frac_of_pattern"], 4)},
         "cpu_baseline": cpu,
         "batched_sweep": batched,
+        "adjoint": adjoint,
         "legs": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in results.items()},
     }

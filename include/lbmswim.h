@@ -179,6 +179,14 @@ int lbm_set_step_limit(lbm_ctx *ctx, int32_t box, int64_t max_steps);
  * (Alg. 2), asynchronously on the context's stream. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
+/* Build the launch sequence that lbm_step(ctx, nsteps) replays (HIP graphs
+ * of LBM_TUNE_GRAPH_STEPS steps and one of the remainder), without launching
+ * any of it, so that a timed lbm_step does not include capturing graphs.
+ * Graphs are kept until the tuning, the timing mode or the set of active
+ * boxes changes; lbm_step builds what is missing itself.  Synchronising only
+ * when the active boxes changed since the last call. */
+int lbm_prepare(lbm_ctx *ctx, int64_t nsteps);
+
 /* Hydrodynamic force and torque on every body from the last step
  * (Eq. hydroF), nb x 3 doubles each.  on_device = 1: F and T are device
  * pointers and the copy is enqueued; on_device = 0: host pointers and the
@@ -267,8 +275,9 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *                         out tiles in order.  Default 1 when the context's
  *                         two population buffers hold more than 2 GiB in all,
  *                         else 0.  Results are identical.
- *   LBM_TUNE_GRAPH_STEPS  0: launch every kernel; n > 0 (default 32): replay a
- *                         captured HIP graph of n steps where possible
+ *   LBM_TUNE_GRAPH_STEPS  0: launch every kernel; n > 0 (default 32): replay
+ *                         captured HIP graphs of n steps, and the remainder of
+ *                         a run as one graph of its own length
  *   LBM_TUNE_FULL_REMAP   1: map the bodies every step even when no cell can
  *                         have changed side (default 0; results are identical)
  *   LBM_TUNE_NONTEMPORAL  1: streaming (non-temporal) loads of the

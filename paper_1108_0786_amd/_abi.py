@@ -16,7 +16,7 @@ TRAJ_DOUBLES = 16
 
 SYMBOLS = [
     "lbm_init", "lbm_init_batch", "lbm_set_bodies", "lbm_set_bodies_box", "lbm_set_step_limit",
-    "lbm_step", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
+    "lbm_step", "lbm_prepare", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
     "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations",
     "lbm_flow_average_begin", "lbm_flow_average_get", "lbm_step_count",
     "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_vacuum_run",
@@ -79,6 +79,7 @@ def load():
                                 P(LbmDrive), C.c_int32], C.c_int),
         "lbm_set_step_limit": ([ctx_p, C.c_int32, C.c_int64], C.c_int),
         "lbm_step": ([ctx_p, C.c_int64], C.c_int),
+        "lbm_prepare": ([ctx_p, C.c_int64], C.c_int),
         "lbm_body_forces": ([ctx_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
         "lbm_body_forces_box": ([ctx_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
         "lbm_get_bodies": ([ctx_p, P(LbmBody), C.c_int32], C.c_int),

@@ -113,6 +113,33 @@ template <> struct Storage<bf16_t> {
     }
 };
 
+// Sums over the 64 lanes of a wave in a fixed xor-shuffle tree: every lane
+// gets the same total, and the order of the additions does not depend on
+// timing.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// The owners of the 18 neighbours of a cell (0 fluid, 1 + b body b), five
+// bits each, six to a word: three registers, and no array that a run-time
+// direction would have to index in private memory.
+struct Owners {
+    unsigned w[3] = {0u, 0u, 0u};
+    __device__ __forceinline__ int get(int a) const {
+        const int q = (a - 1) / 6, sh = 5 * ((a - 1) % 6);
+        const unsigned word = q == 0 ? w[0] : (q == 1 ? w[1] : w[2]);
+        return (int)((word >> sh) & 31u);
+    }
+    __device__ __forceinline__ void set(int a, int v) { w[(a - 1) / 6] |= (unsigned)v << (5 * ((a - 1) % 6)); }
+};
+
 // ---------------------------------------------------------------------------
 // Device tables
 // ---------------------------------------------------------------------------
@@ -136,14 +163,30 @@ struct DevDrive {
     long long off_left, off_right;
 };
 
-// Momentum-exchange contribution of one boundary link (Eq. hydroF), written
-// by the sweep: deviation part of e_alpha [2 f~ + 6 w rho e_opp.u_w] and its
-// torque about the body position, plus the integer geometric torque term
-// (2 d + 1) x (36 * 2 w_alpha e_alpha), d the integer lever offset.
+// Momentum-exchange contribution of one boundary link (Eq. hydroF), scratch
+// of the sweep: deviation part of e_alpha [2 f~ + 6 w rho e_opp.u_w] and its
+// torque about the body position, the integer geometric torque term
+// (2 d + 1) x (36 * 2 w_alpha e_alpha), d the integer lever offset, and the
+// link's direction alpha.
 struct LinkRec {
     double f[3];
     double t[3];
     int s[3];
+    int a;
+};
+
+// Momentum-exchange sums (Eq. hydroF) of one body over the boundary links of
+// one wave of 64 consecutive cells, written by the sweep: the deviation part
+// of e_alpha [2 f~ + 6 w rho e_opp.u_w] and its torque about the body
+// position, and the exact integer sums of the geometric term 2 w_alpha
+// e_alpha: torque (2 d + 1) x (36 * 2 w_alpha e_alpha), d the integer lever
+// offset, and force 36 * 2 w_alpha e_alpha.
+struct ForceRec {
+    double f[3];
+    double t[3];
+    int s[3];
+    int g[3];
+    int body;
     int pad;
 };
 
@@ -164,7 +207,9 @@ struct BoxDesc {
     uint8_t *old_owner;        // N bytes: owner before the last remap
     int *link_cell;
     signed char *link_dir, *link_body;
-    LinkRec *link_rec;         // one record per link, written by the sweep
+    LinkRec *link_rec;         // one scratch record per link, written and summed by the sweep
+    ForceRec *frec;            // momentum-exchange sums per (wave, body), by body, written by the sweep
+    int *grp_pos;              // record of the wave's q-th body at the wave's first link + q
     int *link_base;            // N ints: first link of a boundary cell
     int link_cap;
     int force_avg;             // 1: bodies move with the mean of this and the last step's F, T
@@ -173,7 +218,6 @@ struct BoxDesc {
     DevDrive *drives;
     double *traj;
     long long traj_cap;
-    void *partials;            // momentum-exchange partial sums, one slice per reduction workgroup
     void *ctl;                 // control words of the coupling kernel (counter, barrier, remap slices)
     double *flow_sum;          // 3 arrays of N: summed fluid velocity (x, y, z) for the time average, or null
     int *flow_count;           // N: samples in which the cell was fluid
@@ -184,6 +228,7 @@ struct BoxDesc {
     int cur;                   // index of the buffer holding the current populations
     int link_count;
     int status;                // 0 ok, else an lbm error code
+    int rec_off[17];           // momentum-exchange records of body b: [rec_off[b], rec_off[b + 1])
 };
 
 }  // namespace lbm

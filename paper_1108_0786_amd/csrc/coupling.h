@@ -1,27 +1,27 @@
 // Per-box coupling kernel, run after each sweep:
 //   1. momentum-exchange force and torque of every body (Eq. hydroF): the
-//      link records written by the sweep are summed by kRedBlocks workgroups
-//      per box into partials, in a fixed order; the geometric part 2 w e of
-//      the link term is accumulated exactly in integers;
-//   2. the last workgroup to finish (a global counter) adds the partials in
-//      block order, adds the driving forces (Eqs. FB1-FB3) and the
+//      sweep has summed the links of every wave of 64 cells into one record
+//      per (wave, body); the box's first workgroup adds the records of each
+//      body in a fixed order, and the geometric part 2 w e of the link term,
+//      which the records carry as exact integers;
+//   2. the same workgroup adds the driving forces (Eqs. FB1-FB3) and the
 //      spring-damper forces (Eqs. osci_i/j) and advances every body by one
 //      semi-implicit Euler step (Alg. 1);
 //   3. the bodies are mapped for the next step (Sec. 2.3): new flags, refill
-//      of uncovered cells, near-body marks and the boundary links, skipped
-//      when no cell can have changed side since the last mapping.  When all
-//      workgroups of the launch can be resident at once, the box's
-//      kRedBlocks workgroups wait for the decision and share the mapping
-//      (cooperative); otherwise the finishing workgroup maps alone.
-// All sums are in a fixed order, so results do not depend on which
-// workgroup finishes last.
+//      of uncovered cells, near-body marks, the boundary links and the
+//      records of the next momentum-exchange sums, skipped when no cell can
+//      have changed side since the last mapping.  When all workgroups of the
+//      launch can be resident at once, the box's kRedBlocks workgroups wait
+//      for the decision and share the mapping (cooperative); otherwise the
+//      first workgroup maps alone.
+// All sums are in a fixed order, so results do not depend on the launch.
 #pragma once
 #include "geometry.h"
 
 namespace lbm {
 
 constexpr int kCoupleThreads = 256;
-constexpr int kRedBlocks = 32;  // reduction workgroups per box
+constexpr int kRedBlocks = 32;  // workgroups per box in a coupling launch (they share a remap)
 constexpr int kMaxBodies = 16;
 constexpr int kMaxSprings = 64;
 constexpr int kMaxDrives = 16;
@@ -33,27 +33,19 @@ enum : int { kModeStep = 0, kModeMapOnly = 1 };
 // Control words of one box's coupling launch, in device memory, zeroed when
 // the box is set up.
 struct CoupleCtl {
-    int counter;                 // reduction workgroups of the current step that have finished
     unsigned arrived, gen;       // barrier of the box's workgroups: arrivals, generation
-    int map_req, cur;            // published by the finishing workgroup: remap needed, buffer index
-    int share;                   // set by the last step: this step's workgroups stay to share a remap
+    int map_req, cur;            // published by the first workgroup: remap needed, buffer index
+    unsigned launches;           // workgroups of this box's coupling launches so far (kRedBlocks each)
+    int share[2];                // set by the previous launch, by launch parity: the workgroups stay
+                                 // to share a remap
     int lo[3], hi[3];            // ... and the cell box to map
     int counts[kRedBlocks];      // links found in each workgroup's slice of the cell box
     unsigned long long margin[kMaxBodies];  // bits of each body's margin (a non-negative double)
     unsigned owner_changes;      // cells whose owner a mapping has changed, counted since set-up
 };
 
-// partial momentum-exchange sums of one body over one slice of the links:
-// F (3), T (3) in double; S (3), G (3) exact integers
-struct Partial {
-    double v[6];
-    long long iv[6];
-};
-
 struct CoupleShared {
-    double wred[kCoupleThreads / 64][3][6];
-    int wredi[kCoupleThreads / 64][3][6];
-    double drv[kMaxDrives][3];  // driving forces of each drive: left, right, middle (x components)
+    double drv[kMaxDrives][2];  // driving forces of each drive: left, right (x components)
     double spr[kMaxSprings][3]; // force of each spring on its body i (body j feels the opposite)
     int bad[kMaxBodies];
     double red[kCoupleThreads];
@@ -61,7 +53,8 @@ struct CoupleShared {
     double F[kMaxBodies][3], T[kMaxBodies][3];
     int lo[3], hi[3];          // cell box the remap scans (when map_req)
     int map_req;               // 1: this step ends with a remap
-    int last;
+    int ltotal;                // links of the box after the remap
+    int parity, hint;          // this launch's parity and share hint
     int sync_ok;               // 0: a barrier of the cooperative remap timed out
     int first;                 // number of the first link of this workgroup's slice
     int share_next;            // the next step may remap: its workgroups should stay
@@ -75,7 +68,7 @@ struct CoupleShared {
     double margin[kMaxBodies];
     double qmap[kMaxBodies][4];
     double psum[kMaxBodies][6];
-    long long psumi[kMaxBodies][6];
+    int psumi[kMaxBodies][6];
 };
 
 __device__ __forceinline__ double block_min(double v, CoupleShared &sh) {
@@ -111,118 +104,61 @@ __device__ __forceinline__ double load_dev(const void *p, size_t i, float inv_sc
     return (double)Storage<S>::load((const S *)p, i, inv_scale);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
-// 1. momentum exchange: workgroup r of a box sums the links
-//    l = r * T + t + k * R * T (T threads, R workgroups), all bodies at once
+// 1. momentum exchange: the sweep's records, body by body
 // ---------------------------------------------------------------------------
-constexpr int kBodyGroup = 3;   // bodies accumulated per pass over the links
-
-__device__ void reduce_links(const BoxDesc &B, int r, CoupleShared &sh) {
-    const int L = min(B.link_count, B.link_cap);
+// The records of body b are [rec_off[b], rec_off[b + 1]).  Wave w of the
+// workgroup adds those of bodies w, w + 4, ...: lane l takes records l,
+// l + 64, ... of the range in that order (four loads in flight), and the
+// lanes are added in a fixed xor-shuffle tree.  The sums go to sh.psum /
+// sh.psumi; the body table is not needed yet, so this runs while the tables
+// are being staged.
+// B is the kernel's snapshot of the descriptor and Bg the descriptor itself:
+// the offsets are read from Bg, as an index into the snapshot's array would
+// move the whole snapshot out of registers.
+__device__ void sum_records(const BoxDesc &B, const BoxDesc &Bg, CoupleShared &sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    Partial *out = (Partial *)B.partials + (size_t)r * kMaxBodies;
-    for (int b0 = 0; b0 < B.nb; b0 += kBodyGroup) {
-        double acc[kBodyGroup][6];
-        int ia[kBodyGroup][6];
+    for (int b = wave; b < B.nb; b += kCoupleThreads / 64) {
+        const int h0 = min(Bg.rec_off[b], B.link_cap), h1 = min(Bg.rec_off[b + 1], B.link_cap);
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int ia[6] = {0, 0, 0, 0, 0, 0};
+        for (int h = h0 + lane; h < h1; h += 4 * 64) {
+            ForceRec rec[4];
 #pragma unroll
-        for (int q = 0; q < kBodyGroup; ++q)
+            for (int u = 0; u < 4; ++u)
+                if (h + 64 * u < h1) rec[u] = B.frec[h + 64 * u];
 #pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                acc[q][v] = 0.0;
-                ia[q][v] = 0;
-            }
-        for (int l = r * kCoupleThreads + (int)threadIdx.x; l < L; l += kRedBlocks * kCoupleThreads) {
-            const int bb = B.link_body[l] - b0;
-            const int a = B.link_dir[l];
-            const LinkRec rec = B.link_rec[l];
-            const int cw = two_w36(a);
-            const int ge[3] = {ex(a) * cw, ey(a) * cw, ez(a) * cw};
+            for (int u = 0; u < 4; ++u)
+                if (h + 64 * u < h1)
 #pragma unroll
-            for (int q = 0; q < kBodyGroup; ++q) {
-                const bool m = bb == q;
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    acc[q][v] += m ? rec.f[v] : 0.0;
-                    acc[q][3 + v] += m ? rec.t[v] : 0.0;
-                    ia[q][v] += m ? rec.s[v] : 0;
-                    ia[q][3 + v] += m ? ge[v] : 0;
-                }
-            }
+                    for (int v = 0; v < 3; ++v) {
+                        acc[v] += rec[u].f[v];
+                        acc[3 + v] += rec[u].t[v];
+                        ia[v] += rec[u].s[v];
+                        ia[3 + v] += rec[u].g[v];
+                    }
         }
-        // fixed reduction tree: lanes by xor-shuffle, then waves in order
 #pragma unroll
-        for (int q = 0; q < kBodyGroup; ++q)
-#pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                acc[q][v] = wave_sum(acc[q][v]);
-                ia[q][v] = wave_sum_int(ia[q][v]);
-            }
+        for (int v = 0; v < 6; ++v) {
+            acc[v] = wave_sum(acc[v]);
+            ia[v] = wave_sum_int(ia[v]);
+        }
         if (lane == 0)
 #pragma unroll
-            for (int q = 0; q < kBodyGroup; ++q)
-#pragma unroll
-                for (int v = 0; v < 6; ++v) {
-                    sh.wred[wave][q][v] = acc[q][v];
-                    sh.wredi[wave][q][v] = ia[q][v];
-                }
-        __syncthreads();
-        if (threadIdx.x < kBodyGroup * 12) {
-            const int q = threadIdx.x / 12, v = threadIdx.x % 12;
-            if (b0 + q < B.nb) {
-                if (v < 6) {
-                    double t = sh.wred[0][q][v];
-                    for (int w = 1; w < kCoupleThreads / 64; ++w) t = t + sh.wred[w][q][v];
-                    out[b0 + q].v[v] = t;
-                } else {
-                    long long t = sh.wredi[0][q][v - 6];
-                    for (int w = 1; w < kCoupleThreads / 64; ++w) t += sh.wredi[w][q][v - 6];
-                    out[b0 + q].iv[v - 6] = t;
-                }
+            for (int v = 0; v < 6; ++v) {
+                sh.psum[b][v] = acc[v];
+                sh.psumi[b][v] = ia[v];
             }
-        }
-        __syncthreads();
     }
 }
 
-// Force and torque of every body from the partials of all slices, summed in
-// slice order.  Thread (b, v) loads the kRedBlocks partials of value v of
-// body b at once (independent loads), then body b's thread assembles them.
+// Force and torque of every body: the deviation sums plus the geometric
+// part, G = (integer sum) / 36 and its torque S / 72 - f x G, f the
+// fractional part of the body position (lever arms are taken from the cell
+// R = floor(X)).  Needs the body table in LDS and sum_records done.
 __device__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
-    const Partial *p = (const Partial *)B.partials;
-    const int t = threadIdx.x;
-    if (t < B.nb * 12) {
-        const int b = t / 12, v = t % 12;
-        if (v < 6) {
-            double x[kRedBlocks];
-#pragma unroll
-            for (int r = 0; r < kRedBlocks; ++r) x[r] = p[(size_t)r * kMaxBodies + b].v[v];
-            double tot = x[0];
-#pragma unroll
-            for (int r = 1; r < kRedBlocks; ++r) tot = tot + x[r];
-            sh.psum[b][v] = tot;
-        } else {
-            long long x[kRedBlocks];
-#pragma unroll
-            for (int r = 0; r < kRedBlocks; ++r) x[r] = p[(size_t)r * kMaxBodies + b].iv[v - 6];
-            long long tot = 0;
-#pragma unroll
-            for (int r = 0; r < kRedBlocks; ++r) tot += x[r];
-            sh.psumi[b][v - 6] = tot;
-        }
-    }
-    __syncthreads();
-    const int b = t;
+    const int b = threadIdx.x;
     if (b < B.nb) {
 #pragma clang fp contract(off)
         const DevBody &bd = sh.body[b];
@@ -252,22 +188,26 @@ __device__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
     const int nb = B.nb;
     const long long n = B.step;
     const int t = threadIdx.x;
-    // driving, Eqs. FB1-FB3 (delayed right force): one thread per drive
+    // driving, Eqs. FB1-FB3 (delayed right force): the left force of drive d
+    // by thread d of the first wave, the right force by thread d of the
+    // second, so that the two sines are evaluated side by side
     if (t < B.nd) {
         const DevDrive &dv = sh.drive[t];
         const double om = 2.0 * M_PI / dv.period;
         double fl = -dv.amplitude * sin(om * (double)n);
+        if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
+        sh.drv[t][0] = fl;
+    } else if (t >= 64 && t - 64 < B.nd) {
+        const DevDrive &dv = sh.drive[t - 64];
+        const double om = 2.0 * M_PI / dv.period;
         double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
         if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
-        if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
         if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
-        sh.drv[t][0] = fl;
-        sh.drv[t][1] = fr;
-        sh.drv[t][2] = -(fl + fr);
+        sh.drv[t - 64][1] = fr;
     }
     // springs, Eqs. spring_i, damp_i, osci_i/j: one thread per spring, in the
-    // second wave
-    const int e = t - 64;
+    // third wave
+    const int e = t - 128;
     if (e >= 0 && e < B.ns) {
         const DevSpring &sp = sh.spring[e];
         const DevBody &bi = sh.body[sp.i];
@@ -288,9 +228,10 @@ __device__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
         double Fd[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < B.nd; ++k) {
             const DevDrive &dv = sh.drive[k];
-            if (dv.left == b) Fd[0] = Fd[0] + sh.drv[k][0];
-            if (dv.right == b) Fd[0] = Fd[0] + sh.drv[k][1];
-            if (dv.middle == b) Fd[0] = Fd[0] + sh.drv[k][2];
+            const double fl = sh.drv[k][0], fr = sh.drv[k][1];
+            if (dv.left == b) Fd[0] = Fd[0] + fl;
+            if (dv.right == b) Fd[0] = Fd[0] + fr;
+            if (dv.middle == b) Fd[0] = Fd[0] + -(fl + fr);
         }
         for (int k = 0; k < B.ns; ++k) {
             const DevSpring &sp = sh.spring[k];
@@ -613,7 +554,7 @@ __device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, in
         const int t = base + (int)threadIdx.x;
         int c = -1, cnt = 0;
         unsigned mask = 0;
-        unsigned char owners[19];
+        Owners owners;
         if (t < t1) {
             int i, j, k;
             map_cell(m, t, i, j, k);
@@ -638,7 +579,7 @@ __device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, in
 #pragma unroll
                 for (int a = 1; a < 19; ++a) {
                     const int o = (ok >> a) & 1u ? nf[a] & kOwnerMask : 0;
-                    owners[a] = (unsigned char)o;
+                    owners.set(a, o);
                     if (o) {
                         mask |= 1u << a;
                         ++cnt;
@@ -653,12 +594,12 @@ __device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, in
             if (cnt) {
                 B.link_base[c] = off;
                 int l = off;
-                for (int a = 1; a < 19; ++a) {
-                    if (!(mask & (1u << a))) continue;
+                for (unsigned m = mask; m; m &= m - 1) {
+                    const int a = __builtin_ctz(m);
                     if (l < B.link_cap) {
                         B.link_cell[l] = c;
                         B.link_dir[l] = (signed char)a;
-                        B.link_body[l] = (signed char)(owners[a] - 1);
+                        B.link_body[l] = (signed char)(owners.get(a) - 1);
                     }
                     ++l;
                 }
@@ -667,6 +608,54 @@ __device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, in
         running += tot;
     }
     return running - first;
+}
+
+// The records of the momentum-exchange sums for the new links: one per wave
+// of 64 consecutive cells and body that the wave's links reach, grouped by
+// body and, within a body, in the order of the waves.  The link list is
+// sorted by cell, so the links of a wave are contiguous; the q-th body (in
+// ascending order) of the wave that starts at link l0 finds its record at
+// grp_pos[l0 + q] (q is smaller than the wave's link count, so these slots
+// are the wave's own).  Thread t takes a contiguous range of links and the
+// waves that start in it; one block scan per body numbers the records.
+// Needs the whole link list written.
+__device__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int L) {
+    const int chunk = (L + kCoupleThreads - 1) / kCoupleThreads;
+    const int l0 = min((int)threadIdx.x * chunk, L), l1 = min(l0 + chunk, L);
+    auto wave_mask = [&](int l, int w) {
+        unsigned m = 0;
+        for (int q = l; q < L && (B.link_cell[q] >> 6) == w; ++q) m |= 1u << B.link_body[q];
+        return m;
+    };
+    auto starts_wave = [&](int l, int w) { return l == 0 || (B.link_cell[l - 1] >> 6) != w; };
+    // records of each body among the waves that start in this thread's range
+    unsigned seen = 0;   // bodies with a record here
+    for (int l = l0; l < l1; ++l) {
+        const int w = B.link_cell[l] >> 6;
+        if (starts_wave(l, w)) seen |= wave_mask(l, w);
+    }
+    int off = 0;   // records of the bodies before b
+    for (int b = 0; b < B.nb; ++b) {
+        int mine = 0;
+        if (seen & (1u << b))
+            for (int l = l0; l < l1; ++l) {
+                const int w = B.link_cell[l] >> 6;
+                if (starts_wave(l, w)) mine += (wave_mask(l, w) >> b) & 1u;
+            }
+        int total;
+        int next = off + block_scan(mine, &total, sh);
+        if (seen & (1u << b))
+            for (int l = l0; l < l1; ++l) {
+                const int w = B.link_cell[l] >> 6;
+                if (!starts_wave(l, w)) continue;
+                const unsigned m = wave_mask(l, w);
+                if ((m >> b) & 1u) B.grp_pos[l + __popc(m & ((1u << b) - 1u))] = next++;
+            }
+        if (threadIdx.x == 0) Bg.rec_off[b] = off;
+        off += total;
+    }
+    if (threadIdx.x == 0)
+        for (int b = B.nb; b <= kMaxBodies; ++b) Bg.rec_off[b] = off;
 }
 
 // Record the positions and orientations the mapping used (the remap skip
@@ -699,6 +688,9 @@ __device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, doubl
         Bg.link_count = total;
         if (total > B.link_cap) Bg.status = -6;
     }
+    __threadfence_block();
+    __syncthreads();
+    map_groups(B, Bg, sh, min(total, B.link_cap));
 }
 
 // Barrier over the kRedBlocks workgroups of one box.  A cooperative launch
@@ -773,6 +765,7 @@ __device__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, Coup
             total += n;
         }
         sh.first = first;
+        sh.ltotal = total;
         if (r == kRedBlocks - 1) {
             Bg.link_count = total;
             if (total > B.link_cap) Bg.status = -6;
@@ -780,6 +773,9 @@ __device__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, Coup
     }
     __syncthreads();
     map_links(B, sh, m, t0, t1, sh.first, true);
+    // the records of the next momentum-exchange sums need every slice's links
+    if (!box_barrier(ctl, sh, Bg)) return;
+    if (r == 0) map_groups(B, Bg, sh, min(sh.ltotal, B.link_cap));
 }
 
 
@@ -789,14 +785,30 @@ __device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes
     for (int t = threadIdx.x; t < n; t += kCoupleThreads) ((int *)dst)[t] = ((const int *)src)[t];
 }
 
-// Stage the box's small tables in LDS: one pass over the words of all five
-// tables together, so that each thread issues its loads at once instead of
-// one table after the other.
-__device__ void stage_in(const BoxDesc &B, CoupleShared &sh, const double *qmaps, const double *margins) {
+// Stage the box's small tables in LDS.  Each thread first loads its words of
+// all five tables into registers (stage_load: the loads of every table are
+// in flight together, and other work, the momentum-exchange sums, can be
+// issued before they return), then stores them (stage_store).
+constexpr int kStageWords = 8;
+static_assert(kStageWords * kCoupleThreads >=
+                  (int)(sizeof(DevBody) * kMaxBodies + sizeof(DevSpring) * kMaxSprings +
+                        sizeof(DevDrive) * kMaxDrives) / 4 + 10 * kMaxBodies,
+              "every word of the tables must have a thread");
+
+struct Staged {
+    int w[kStageWords];
+};
+
+template <bool LOAD>
+__device__ __forceinline__ void stage_words(const BoxDesc &B, CoupleShared &sh, const double *qmaps,
+                                            const double *margins, Staged &st) {
     const int n0 = (int)sizeof(DevBody) * B.nb / 4, n1 = (int)sizeof(DevSpring) * B.ns / 4;
     const int n2 = (int)sizeof(DevDrive) * B.nd / 4, n3 = 2 * B.nb, n4 = 8 * B.nb;
     const int total = n0 + n1 + n2 + n3 + n4;
-    for (int t = threadIdx.x; t < total; t += kCoupleThreads) {
+#pragma unroll
+    for (int k = 0; k < kStageWords; ++k) {
+        const int t = (int)threadIdx.x + k * kCoupleThreads;
+        if (t >= total) continue;
         int w = t;
         const int *src;
         int *dst;
@@ -817,8 +829,19 @@ __device__ void stage_in(const BoxDesc &B, CoupleShared &sh, const double *qmaps
             src = (const int *)qmaps;
             dst = (int *)sh.qmap;
         }
-        dst[w] = src[w];
+        if constexpr (LOAD) st.w[k] = src[w];
+        else dst[w] = st.w[k];
     }
+}
+
+__device__ __forceinline__ void stage_load(const BoxDesc &B, CoupleShared &sh, const double *qmaps,
+                                           const double *margins, Staged &st) {
+    stage_words<true>(B, sh, qmaps, margins, st);
+}
+
+__device__ __forceinline__ void stage_store(const BoxDesc &B, CoupleShared &sh, const double *qmaps,
+                                            const double *margins, Staged &st) {
+    stage_words<false>(B, sh, qmaps, margins, st);
     __syncthreads();
 }
 
@@ -843,44 +866,42 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     CoupleCtl *ctl = (CoupleCtl *)B.ctl;
     double *qm = qmaps + (size_t)bi * 4 * kMaxBodies;
     double *mg = margins + (size_t)bi * kMaxBodies;
-    // the box's workgroups stay to share a remap only if the last step found
-    // that one may come (a remap it did not foresee is done by the finishing
-    // workgroup alone)
-    const int hint = __hip_atomic_load(&ctl->share, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const bool share = coop && (mode == kModeMapOnly || force_map || hint != 0);
-    bool lead;
-    if (mode == kModeStep) {
-        reduce_links(B, r, sh);
-        // the last workgroup of this box to finish goes on
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) sh.last = atomicAdd(&ctl->counter, 1) == kRedBlocks - 1;
-        __syncthreads();
-        lead = sh.last != 0;
-        if (lead) {
-            __threadfence();
-            if (threadIdx.x == 0) {
-                ctl->counter = 0;
-                sh.cur = B.cur;
-            }
-            stage_in(B, sh, qm, mg);
+    // the box's other workgroups stay to share a remap only if the previous
+    // launch found that one may come (a remap it did not foresee is done by
+    // the first workgroup alone).  The hint is kept per launch parity, and
+    // the parity is counted by the workgroups themselves, so that every
+    // workgroup of a launch reads the same hint however late it starts: the
+    // first workgroup writes the next launch's hint while others of this
+    // launch may still be about to read theirs.
+    // One thread per workgroup counts and reads; the whole workgroup must
+    // take the same decision.
+    if (threadIdx.x == 0) {
+        const unsigned arrival =
+            __hip_atomic_fetch_add(&ctl->launches, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.parity = (int)((arrival / kRedBlocks) & 1u);
+        sh.hint = __hip_atomic_load(&ctl->share[sh.parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int parity = sh.parity;
+    const bool share = coop && (mode == kModeMapOnly || force_map || sh.hint != 0);
+    const bool lead = r == 0;
+    if (!share && !lead) return;
+    if (lead) {
+        if (threadIdx.x == 0) sh.cur = B.cur;
+        Staged st;
+        stage_load(B, sh, qm, mg, st);
+        if (mode == kModeStep) sum_records(B, Bg, sh);
+        stage_store(B, sh, qm, mg, st);
+        if (mode == kModeStep) {
             finish_forces(B, sh);
             rigid_step(B, Bg, sh);
         }
-    } else {
-        lead = r == 0;
-        if (lead) {
-            if (threadIdx.x == 0) sh.cur = B.cur;
-            stage_in(B, sh, qm, mg);
-        }
     }
-    if (!share && !lead) return;
     if (lead) {
         if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
         stage_out(B, sh);
-        // every other workgroup has read this step's hint before the leader
-        // was known, so the next step's may be stored now
-        if (threadIdx.x == 0) ctl->share = sh.share_next;
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&ctl->share[parity ^ 1], sh.share_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!share) {
             if (sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
             return;

@@ -39,10 +39,11 @@ struct HostBox {
     DevDrive *d_drives = nullptr;
     int *link_cell = nullptr;
     signed char *link_dir = nullptr, *link_body = nullptr;
-    LinkRec *link_rec = nullptr;
+    LinkRec *link_rec = nullptr; // momentum-exchange scratch of the sweep, one per link
+    ForceRec *frec = nullptr;    // momentum-exchange records, one per (wave, body)
+    int *grp_pos = nullptr;      // per link: record of a wave's q-th body at its first link + q
     int *link_base = nullptr;
     uint8_t *old_owner = nullptr;
-    void *partials = nullptr;
     CoupleCtl *ctl = nullptr;
     double *flow_sum = nullptr;  // time-averaged flow: 3N sums and N counts (library-owned)
     int *flow_count = nullptr;
@@ -76,8 +77,10 @@ struct lbm_ctx {
     int nontemporal = 0;
     int graph_steps = kDefaultGraphSteps;
     int ngrid = 0;                 // sweep grid (tiles padded to a multiple of 8)
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;    // graph_steps steps
     int graph_len = 0;
+    hipGraphExec_t tail = nullptr;     // the remainder of the last run shorter than graph_steps
+    int tail_len = 0;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
     // adjoint scratch
     void *adj_ckpt = nullptr, *adj_seg = nullptr;
@@ -168,6 +171,8 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.link_dir = h.link_dir;
     d.link_body = h.link_body;
     d.link_rec = h.link_rec;
+    d.frec = h.frec;
+    d.grp_pos = h.grp_pos;
     d.link_base = h.link_base;
     d.link_cap = h.link_cap;
     d.force_avg = h.p.force_average;
@@ -176,7 +181,6 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.drives = h.d_drives;
     d.traj = h.p.traj;
     d.traj_cap = h.p.traj ? h.p.traj_cap : 0;
-    d.partials = h.partials;
     d.ctl = h.ctl;
     d.flow_sum = h.flow_sum;
     d.flow_count = h.flow_count;
@@ -229,7 +233,6 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
         h.stride = params[b].stride ? params[b].stride : h.N;
         if (hipMalloc(&h.link_base, sizeof(int) * h.N) != hipSuccess ||
             hipMalloc(&h.old_owner, h.N) != hipSuccess ||
-            hipMalloc(&h.partials, sizeof(Partial) * kRedBlocks * kMaxBodies) != hipSuccess ||
             hipMalloc(&h.ctl, sizeof(CoupleCtl)) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "out of device memory for per-cell scratch");
@@ -237,7 +240,6 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
         if (hipMemsetAsync(h.p.flags, 0, h.N, c->stream) != hipSuccess ||
             hipMemsetAsync(h.old_owner, 0, h.N, c->stream) != hipSuccess ||
             hipMemsetAsync(h.link_base, 0, sizeof(int) * h.N, c->stream) != hipSuccess ||
-            hipMemsetAsync(h.partials, 0, sizeof(Partial) * kRedBlocks * kMaxBodies, c->stream) != hipSuccess ||
             hipMemsetAsync(h.ctl, 0, sizeof(CoupleCtl), c->stream) != hipSuccess) {
             *out = c;
             return fail(c, LBM_E_HIP, "clearing flags failed");
@@ -414,8 +416,11 @@ int launch_couple(lbm_ctx *c, const int *active_dev, int nactive, int mode) {
 
 void drop_graph(lbm_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->tail) (void)hipGraphExecDestroy(c->tail);
     c->graph = nullptr;
     c->graph_len = 0;
+    c->tail = nullptr;
+    c->tail_len = 0;
 }
 
 // Rebuild the sweep tiles and the active-box list for boxes that still run.
@@ -498,11 +503,14 @@ int launch_step(lbm_ctx *c) {
     return launch_couple(c, c->d_active, c->nactive, kModeStep);
 }
 
-// Capture `len` steps into a graph.  The launches are captured on a private
-// stream (the caller's stream may be the legacy default stream, which cannot
-// be captured); the graph is then launched on the caller's stream.
-int capture_graph(lbm_ctx *c, int len) {
-    drop_graph(c);
+// Capture `len` steps into a graph (*out, replacing what it held).  The
+// launches are captured on a private stream (the caller's stream may be the
+// legacy default stream, which cannot be captured); the graph is then
+// launched on the caller's stream.
+int capture_graph(lbm_ctx *c, int len, hipGraphExec_t *out, int *out_len) {
+    if (*out) (void)hipGraphExecDestroy(*out);
+    *out = nullptr;
+    *out_len = 0;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
@@ -521,10 +529,24 @@ int capture_graph(lbm_ctx *c, int len) {
         return rc;
     }
     if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-    c->graph_len = len;
+    *out_len = len;
+    return LBM_OK;
+}
+
+// The graphs a run of `run` steps replays: graph_steps steps at a time, and
+// the remainder as one graph of its own length (kept until another length is
+// needed).  Captures what is missing; launches nothing.
+int ensure_graphs(lbm_ctx *c, int64_t run) {
+    if (c->timing || c->graph_steps <= 0) return LBM_OK;
+    int rc;
+    if (run >= c->graph_steps && (!c->graph || c->graph_len != c->graph_steps))
+        if ((rc = capture_graph(c, c->graph_steps, &c->graph, &c->graph_len))) return rc;
+    const int rem = (int)(run % c->graph_steps);
+    if (rem > 0 && (!c->tail || c->tail_len != rem))
+        if ((rc = capture_graph(c, rem, &c->tail, &c->tail_len))) return rc;
     return LBM_OK;
 }
 
@@ -849,6 +871,60 @@ int adjoint_impl(lbm_ctx *c, int64_t nsteps, int ce, const double *w_host, doubl
     return LBM_OK;
 }
 
+// The input checks of the integrator-only runs (lbm_vacuum_run and its
+// allocation-free variant).
+int validate_vacuum(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
+                    const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
+                    int64_t traj_cap) {
+    if (!bodies || nb < 1 || nb > kMaxBodies || ns < 0 || ns > kMaxSprings || nd < 0 || nd > kMaxDrives ||
+        (ns && !springs) || (nd && !drives) || nsys < 1 || nsys > 65535 || nsteps < 0 || traj_cap < 0 ||
+        (traj && traj_cap == 0))
+        return LBM_E_ARG;
+    for (int s = 0; s < nsys; ++s) {
+        for (int b = 0; b < nb; ++b) {
+            const lbm_body &x = bodies[(size_t)s * nb + b];
+            if (x.kinematic < 0 || x.kinematic > 2 || !(x.mass > 0) || !(x.inertia[0] > 0) || !(x.inertia[1] > 0) ||
+                !(x.inertia[2] > 0))
+                return LBM_E_ARG;
+        }
+        for (int k = 0; k < ns; ++k) {
+            const lbm_spring &x = springs[(size_t)s * ns + k];
+            if (x.i < 0 || x.i >= nb || x.j < 0 || x.j >= nb || x.i == x.j || !(x.rest_len >= 0)) return LBM_E_ARG;
+        }
+        for (int d = 0; d < nd; ++d) {
+            const lbm_drive &x = drives[(size_t)s * nd + d];
+            if (x.left < 0 || x.left >= nb || x.right < 0 || x.right >= nb || x.middle < 0 || x.middle >= nb ||
+                !(x.period > 0))
+                return LBM_E_ARG;
+        }
+    }
+    return LBM_OK;
+}
+
+DevSpring to_dev_spring(const lbm_spring &x) { return {x.i, x.j, x.k, x.gamma, x.rest_len}; }
+
+DevDrive to_dev_drive(const lbm_drive &x) {
+    return {x.left, x.middle, x.right, x.gate_lagged, x.amplitude, x.period, x.phase_lag, (long long)x.off_left,
+            (long long)x.off_right};
+}
+
+// Descriptor of integrator-only system s: its tables in the device arrays
+// given, its slice of the caller's trajectory ring.
+BoxDesc vacuum_desc(int s, int nb, int ns, int nd, DevBody *bodies, DevSpring *springs, DevDrive *drives, double *traj,
+                    int64_t traj_cap) {
+    BoxDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.nb = nb;
+    d.ns = ns;
+    d.nd = nd;
+    d.bodies = bodies + (size_t)s * nb;
+    d.springs = springs + (size_t)s * ns;
+    d.drives = drives + (size_t)s * nd;
+    d.traj = traj ? traj + (size_t)s * traj_cap * nb * 16 : nullptr;
+    d.traj_cap = traj ? traj_cap : 0;
+    return d;
+}
+
 }  // namespace
 
 extern "C" {
@@ -872,37 +948,13 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
 int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
                    const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
                    int64_t traj_cap, lbm_body *out, void *stream) {
-    if (!bodies || nb < 1 || nb > kMaxBodies || ns < 0 || ns > kMaxSprings || nd < 0 || nd > kMaxDrives ||
-        (ns && !springs) || (nd && !drives) || nsys < 1 || nsys > 65535 || nsteps < 0 || traj_cap < 0 ||
-        (traj && traj_cap == 0))
-        return LBM_E_ARG;
-    for (int s = 0; s < nsys; ++s) {
-        for (int b = 0; b < nb; ++b) {
-            const lbm_body &x = bodies[(size_t)s * nb + b];
-            if (x.kinematic < 0 || x.kinematic > 2 || !(x.mass > 0) || !(x.inertia[0] > 0) || !(x.inertia[1] > 0) ||
-                !(x.inertia[2] > 0))
-                return LBM_E_ARG;
-        }
-        for (int k = 0; k < ns; ++k) {
-            const lbm_spring &x = springs[(size_t)s * ns + k];
-            if (x.i < 0 || x.i >= nb || x.j < 0 || x.j >= nb || x.i == x.j || !(x.rest_len >= 0)) return LBM_E_ARG;
-        }
-        for (int d = 0; d < nd; ++d) {
-            const lbm_drive &x = drives[(size_t)s * nd + d];
-            if (x.left < 0 || x.left >= nb || x.right < 0 || x.right >= nb || x.middle < 0 || x.middle >= nb ||
-                !(x.period > 0))
-                return LBM_E_ARG;
-        }
-    }
+    if (int rc = validate_vacuum(bodies, nb, springs, ns, drives, nd, nsys, nsteps, traj, traj_cap)) return rc;
     std::vector<DevBody> db((size_t)nsys * nb);
     std::vector<DevSpring> ds((size_t)nsys * ns);
     std::vector<DevDrive> dd((size_t)nsys * nd);
     for (size_t q = 0; q < db.size(); ++q) db[q] = to_dev(bodies[q]);
-    for (size_t q = 0; q < ds.size(); ++q)
-        ds[q] = {springs[q].i, springs[q].j, springs[q].k, springs[q].gamma, springs[q].rest_len};
-    for (size_t q = 0; q < dd.size(); ++q)
-        dd[q] = {drives[q].left, drives[q].middle, drives[q].right, drives[q].gate_lagged, drives[q].amplitude,
-                 drives[q].period, drives[q].phase_lag, (long long)drives[q].off_left, (long long)drives[q].off_right};
+    for (size_t q = 0; q < ds.size(); ++q) ds[q] = to_dev_spring(springs[q]);
+    for (size_t q = 0; q < dd.size(); ++q) dd[q] = to_dev_drive(drives[q]);
     DevBody *g_bodies = nullptr;
     DevSpring *g_springs = nullptr;
     DevDrive *g_drives = nullptr;
@@ -918,19 +970,7 @@ int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs
         ok(hipMalloc(&g_drives, sizeof(DevDrive) * std::max<size_t>(dd.size(), 1))) &&
         ok(hipMalloc(&g_desc, sizeof(BoxDesc) * nsys))) {
         std::vector<BoxDesc> desc(nsys);
-        for (int s = 0; s < nsys; ++s) {
-            BoxDesc d;
-            std::memset(&d, 0, sizeof(d));
-            d.nb = nb;
-            d.ns = ns;
-            d.nd = nd;
-            d.bodies = g_bodies + (size_t)s * nb;
-            d.springs = g_springs + (size_t)s * ns;
-            d.drives = g_drives + (size_t)s * nd;
-            d.traj = traj ? traj + (size_t)s * traj_cap * nb * 16 : nullptr;
-            d.traj_cap = traj ? traj_cap : 0;
-            desc[s] = d;
-        }
+        for (int s = 0; s < nsys; ++s) desc[s] = vacuum_desc(s, nb, ns, nd, g_bodies, g_springs, g_drives, traj, traj_cap);
         if (ok(hipMemcpyAsync(g_bodies, db.data(), sizeof(DevBody) * db.size(), hipMemcpyHostToDevice, st)) &&
             (ds.empty() || ok(hipMemcpyAsync(g_springs, ds.data(), sizeof(DevSpring) * ds.size(),
                                              hipMemcpyHostToDevice, st))) &&
@@ -1025,11 +1065,15 @@ int lbm_set_bodies_box(lbm_ctx *c, int32_t box, const lbm_body *bodies, int32_t 
             HIP_TRY(c, hipFree(h.link_dir));
             HIP_TRY(c, hipFree(h.link_body));
             HIP_TRY(c, hipFree(h.link_rec));
+            HIP_TRY(c, hipFree(h.frec));
+            HIP_TRY(c, hipFree(h.grp_pos));
         }
         HIP_TRY(c, hipMalloc(&h.link_cell, sizeof(int) * cap));
         HIP_TRY(c, hipMalloc(&h.link_dir, cap));
         HIP_TRY(c, hipMalloc(&h.link_body, cap));
         HIP_TRY(c, hipMalloc(&h.link_rec, sizeof(LinkRec) * cap));
+        HIP_TRY(c, hipMalloc(&h.frec, sizeof(ForceRec) * cap));
+        HIP_TRY(c, hipMalloc(&h.grp_pos, sizeof(int) * cap));
         h.link_cap = (int)cap;
     }
     if (!h.d_bodies) {
@@ -1095,13 +1139,14 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
             if (h.limit >= 0) run = std::min<int64_t>(run, h.limit - h.steps);
         }
         int64_t s = 0;
-        if (!c->timing && c->graph_steps > 0 && run >= c->graph_steps) {
-            if (!c->graph || c->graph_len != c->graph_steps) {
-                rc = capture_graph(c, c->graph_steps);
-                if (rc) return rc;
+        if (!c->timing && c->graph_steps > 0) {
+            if ((rc = ensure_graphs(c, run))) return rc;
+            if (run >= c->graph_steps)
+                for (; s + c->graph_len <= run; s += c->graph_len) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+            if (s < run) {
+                HIP_TRY(c, hipGraphLaunch(c->tail, c->stream));
+                s += c->tail_len;
             }
-            for (; s + c->graph_len <= run; s += c->graph_len)
-                HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
         }
         for (; s < run; ++s) {
             rc = timed(c, 0, [&] { return launch_sweep(c); });
@@ -1117,6 +1162,20 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
         done += run;
     }
     return LBM_OK;
+}
+
+int lbm_prepare(lbm_ctx *c, int64_t nsteps) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(c, LBM_E_ARG, "nsteps < 0");
+    if (c->work_dirty && (rc = rebuild_work(c))) return rc;
+    if (c->nactive == 0 || nsteps == 0) return LBM_OK;
+    int64_t run = nsteps;
+    for (int b : c->active_host) {
+        const HostBox &h = c->boxes[b];
+        if (h.limit >= 0) run = std::min<int64_t>(run, h.limit - h.steps);
+    }
+    return ensure_graphs(c, run);
 }
 
 int lbm_body_forces_box(lbm_ctx *c, int32_t box, double *F, double *T, int32_t on_device) {
@@ -1405,9 +1464,10 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipFree(h.link_dir);
         (void)hipFree(h.link_body);
         (void)hipFree(h.link_rec);
+        (void)hipFree(h.frec);
+        (void)hipFree(h.grp_pos);
         (void)hipFree(h.link_base);
         (void)hipFree(h.old_owner);
-        (void)hipFree(h.partials);
         (void)hipFree(h.ctl);
         (void)hipFree(h.flow_sum);
         (void)hipFree(h.flow_count);

@@ -2,16 +2,31 @@
 // loads the 19 deviations of its cell, collides them with LBGK and pushes
 // the post-collision values to the neighbours; populations that would enter
 // a wall are bounced back (Eq. lbm:bounce_back), those that would enter a
-// body are bounced back with the moving-wall term of Sec. 2.3, and for those
-// the link's momentum-exchange contribution (Eq. hydroF) is written to the
-// link's record.
+// body are bounced back with the moving-wall term of Sec. 2.3, and the
+// momentum exchange of those links (Eq. hydroF) is summed in the sweep
+// itself, per wave of 64 consecutive cells and per body, into one record.
 #pragma once
 #include "geometry.h"
 
 namespace lbm {
 
+// Owners of the 18 neighbours of a near-body cell, loaded before any is
+// used so that their latencies overlap (a neighbour across a wall reads the
+// cell itself, which is fluid).
+__device__ __forceinline__ void neighbour_owners(const BoxDesc &B, int cell, int i, int j, int k, Owners &owner) {
+    int idx[19];
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        int ti, tj, tk;
+        idx[a] = neighbour_rt(a, i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk) ? ti + B.nx * (tj + B.ny * tk) : cell;
+    }
+#pragma unroll
+    for (int a = 1; a < 19; ++a) owner.set(a, B.flags[idx[a]] & kOwnerMask);
+}
+
 // Moving bounce-back of the link (cell, A) into body `owner`: returns the
-// reflected value and writes the link record.
+// reflected value and writes the link's momentum-exchange contribution to
+// its scratch record (summed by the wave in body_links).
 template <typename S, int A>
 __device__ __forceinline__ typename Storage<S>::C bounce_moving(const BoxDesc &B, int cell, int owner,
                                                                 int ti, int tj, int tk,
@@ -43,17 +58,17 @@ __device__ __forceinline__ typename Storage<S>::C bounce_moving(const BoxDesc &B
         rec.s[0] = d1 * e2 - d2 * e1;
         rec.s[1] = d2 * e0 - d0 * e2;
         rec.s[2] = d0 * e1 - d1 * e0;
-        rec.pad = 0;
+        rec.a = A;
         B.link_rec[slot] = rec;
     }
     return (C)val;
 }
 
-// owner[A]: the body behind the link (cell, A), 0 for fluid; only near-body
-// cells look it up.  slot: the cell's next link record.
+// owner.get(A): the body behind the link (cell, A), 0 for fluid; only
+// near-body cells look it up.  slot: the cell's next link.
 template <typename S, int A>
 __device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, long long stride, int cell, int i,
-                                         int j, int k, const uint8_t *owner, typename Storage<S>::C v,
+                                         int j, int k, const Owners &owner, typename Storage<S>::C v,
                                          typename Storage<S>::C rho, int &slot) {
     using St = Storage<S>;
     int ti, tj, tk;
@@ -61,9 +76,9 @@ __device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, long long str
         St::store(dst, (size_t)opp(A) * stride + cell, v, B.scale);
         return;
     }
-    if (owner[A]) {
-        St::store(dst, (size_t)opp(A) * stride + cell,
-                  bounce_moving<S, A>(B, cell, owner[A], ti, tj, tk, v, rho, slot), B.scale);
+    if (const int o = owner.get(A)) {
+        St::store(dst, (size_t)opp(A) * stride + cell, bounce_moving<S, A>(B, cell, o, ti, tj, tk, v, rho, slot),
+                  B.scale);
         ++slot;
         return;
     }
@@ -73,7 +88,7 @@ __device__ __forceinline__ void push_one(const BoxDesc &B, S *dst, long long str
 template <typename S, int A>
 struct PushAll {
     static __device__ __forceinline__ void run(const BoxDesc &B, S *dst, long long stride, int cell, int i,
-                                               int j, int k, const uint8_t *owner,
+                                               int j, int k, const Owners &owner,
                                                const typename Storage<S>::C *f, typename Storage<S>::C rho,
                                                int &slot) {
         push_one<S, A>(B, dst, stride, cell, i, j, k, owner, f[A], rho, slot);
@@ -83,28 +98,106 @@ struct PushAll {
 template <typename S>
 struct PushAll<S, 19> {
     static __device__ __forceinline__ void run(const BoxDesc &, S *, long long, int, int, int, int,
-                                               const uint8_t *, const typename Storage<S>::C *,
+                                               const Owners &, const typename Storage<S>::C *,
                                                typename Storage<S>::C, int &) {}
 };
 
-// Owners of the 18 neighbours of a near-body cell, loaded before any is
-// used so that their latencies overlap (a neighbour across a wall reads the
-// cell itself, which is fluid).
-__device__ __forceinline__ void neighbour_owners(const BoxDesc &B, int cell, int i, int j, int k, uint8_t *owner) {
-    int idx[19];
+// Momentum exchange of the wave's near-body cells (Eq. hydroF), body by
+// body.  Called by every lane of a wave that holds at least one near-body
+// cell, after the pushes: lane l adds the scratch records of its own links
+// into body b (links first .. first + n - 1 of its cell, in direction
+// order), the wave adds the lanes in a fixed xor-shuffle tree, and lane 0
+// writes the sums to the record that the mapping reserved for (this wave,
+// body b): record grp_pos[l0 + q] for the wave's q-th body in ascending
+// order, l0 being the wave's first link.  A wave covers 64 consecutive
+// cells of its box however the sweep is launched, so the sums come out the
+// same bit for bit.  The populations are no longer live here, which keeps
+// the sweep within its register budget.
+// The owners of the cell's neighbours are loaded again here (they were
+// loaded for the pushes moments ago) rather than kept through the pushes.
+__device__ __forceinline__ void body_links(const BoxDesc &B, bool near, int cell, int i, int j, int k) {
+    unsigned lm = 0;
+    int n = 0, first = 0x7fffffff;
+    if (near) {
+        Owners owner;
+        neighbour_owners(B, cell, i, j, k, owner);
 #pragma unroll
-    for (int a = 1; a < 19; ++a) {
-        int ti, tj, tk;
-        idx[a] = neighbour_rt(a, i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk) ? ti + B.nx * (tj + B.ny * tk) : cell;
+        for (int a = 1; a < 19; ++a) {
+            const int o = owner.get(a);
+            lm |= o ? 1u << (o - 1) : 0u;
+            n += o ? 1 : 0;
+        }
+        first = B.link_base[cell];
     }
+    unsigned wm = lm;
+    int l0 = first;
 #pragma unroll
-    for (int a = 1; a < 19; ++a) owner[a] = B.flags[idx[a]] & kOwnerMask;
+    for (int o = 32; o > 0; o >>= 1) {
+        wm |= __shfl_xor(wm, o, 64);
+        l0 = min(l0, __shfl_xor(l0, o, 64));
+    }
+    wm = __builtin_amdgcn_readfirstlane(wm);
+    l0 = __builtin_amdgcn_readfirstlane(l0);
+    for (int q = 0; wm; ++q) {
+        const int b = __builtin_ctz(wm);
+        wm &= wm - 1;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int ia[6] = {0, 0, 0, 0, 0, 0};
+        if (lm & (1u << b)) {
+#pragma unroll 1
+            for (int l = first; l < first + n && l < B.link_cap; ++l) {
+                if (B.link_body[l] != b) continue;
+                const LinkRec rec = B.link_rec[l];
+                const int cw = two_w36(rec.a);
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    acc[v] += rec.f[v];
+                    acc[3 + v] += rec.t[v];
+                    ia[v] += rec.s[v];
+                }
+                ia[3] += ex(rec.a) * cw;
+                ia[4] += ey(rec.a) * cw;
+                ia[5] += ez(rec.a) * cw;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            acc[v] = wave_sum(acc[v]);
+            ia[v] = wave_sum_int(ia[v]);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            const int l = l0 + q;
+            if (l < B.link_cap) {
+                const int pos = B.grp_pos[l];
+                if (pos >= 0 && pos < B.link_cap) {
+                    ForceRec rec;
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        rec.f[v] = acc[v];
+                        rec.t[v] = acc[3 + v];
+                        rec.s[v] = ia[v];
+                        rec.g[v] = ia[3 + v];
+                    }
+                    rec.body = b;
+                    rec.pad = 0;
+                    B.frec[pos] = rec;
+                }
+            }
+        }
+    }
 }
 
 // LBGK collision in deviation form: dF~ = dF + omega (dF_eq - dF),
 // dF_eq = w [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].  Opposite directions
 // share the even part drho + rho (4.5 (e.u)^2 - 1.5 u.u) and differ in the
-// sign of 3 rho e.u.  Every rounding is spelled out (automatic contraction
+// sign of the odd part 3 rho e.u, which is taken as 3 e.j (j = rho u, the
+// momentum summed from the populations): the same number in exact
+// arithmetic, but rho (j / rho) rounds away from j, and in float that
+// rounding does not average out.  It leaks momentum into the fluid in a way
+// correlated with the flow (on the 256x128x128 swimmer it drives a mean
+// drift of 1e-11 per step, twice the swimming speed, in 20 periods); with
+// e.j the float run's per-period swimming velocity stays within 1.3e-6 of
+// the double run's.  Every rounding is spelled out (automatic contraction
 // off, fused multiply-adds written as such), so that the collision gives
 // the same bits in every kernel and code path that inlines it.
 template <typename C>
@@ -132,12 +225,13 @@ __device__ __forceinline__ C edot(C ux, C uy, C uz) {
 }
 
 template <typename C, int A>
-__device__ __forceinline__ void relax_pair(C *f, C drho, C rho, C ux, C uy, C uz, C usq15, C omega) {
+__device__ __forceinline__ void relax_pair(C *f, C drho, C rho, C ux, C uy, C uz, C jx, C jy, C jz, C usq15,
+                                           C omega) {
 #pragma clang fp contract(off)
     constexpr int O = opp(A);
     const C eu = edot<C, A>(ux, uy, uz);
     const C even = fmac(rho, fmac(C(4.5) * eu, eu, -usq15), drho);
-    const C odd = C(3) * rho * eu;
+    const C odd = C(3) * edot<C, A>(jx, jy, jz);
     const C fa = C(wgt(A)) * (even + odd);
     const C fo = C(wgt(A)) * (even - odd);
     f[A] = fmac(omega, fa - f[A], f[A]);
@@ -158,15 +252,15 @@ __device__ __forceinline__ C collide(C *f, C omega) {
     const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
     const C usq15 = C(1.5) * fmac(ux, ux, fmac(uy, uy, uz * uz));
     f[0] = fmac(omega, C(wgt(0)) * (drho - rho * usq15) - f[0], f[0]);
-    relax_pair<C, 1>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 3>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 5>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 7>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 9>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 11>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 13>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 15>(f, drho, rho, ux, uy, uz, usq15, omega);
-    relax_pair<C, 17>(f, drho, rho, ux, uy, uz, usq15, omega);
+    relax_pair<C, 1>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 3>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 5>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 7>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 9>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 11>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 13>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 15>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 17>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
     return rho;
 }
 
@@ -272,8 +366,13 @@ __device__ __forceinline__ int tile_index(int xcd_order) {
     return (w & 7) * per + (w >> 3);
 }
 
+// At least 7 waves per SIMD (72 registers) for the 4- and 2-byte formats,
+// 5 for double, one fewer while sampling the flow average: without the hint
+// the register allocator settles one register above 72 for the float
+// sweep, which costs a wave per SIMD.
 template <typename S, int BLOCK, bool NT, bool FLOW>
-__global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 5 : (FLOW ? 6 : 7), 8)))
+void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
                                                       int xcd_order) {
     using St = Storage<S>;
     using C = typename St::C;
@@ -351,16 +450,22 @@ __global__ __launch_bounds__(BLOCK) void sweep_kernel(BoxDesc *boxes, const Work
             PushFast<S, 1>::run(dst, stride, cell, off_p, off_m, f, B.scale);
         }
     }
-    if (fast || !valid || !fluid) return;
+    // cells on the general path: walls and near-body cells.  Every lane stays
+    // for the wave's momentum-exchange sums.
+    const bool general = valid && fluid && !fast;
+    const bool near = general && (fl & kNearBit);
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
-    St::store(gdst, (size_t)cell, f[0], B.scale);
-    uint8_t owner[19] = {};
-    int slot = 0;
-    if (fl & kNearBit) {
-        neighbour_owners(B, cell, i, j, k, owner);
-        slot = B.link_base[cell];
+    if (general) {
+        St::store(gdst, (size_t)cell, f[0], B.scale);
+        Owners owner;
+        int slot = 0;
+        if (near) {
+            neighbour_owners(B, cell, i, j, k, owner);
+            slot = B.link_base[cell];
+        }
+        PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, owner, f, rho, slot);
     }
-    PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, owner, f, rho, slot);
+    if (__any(near)) body_links(B, near, cell, i, j, k);
 }
 
 }  // namespace lbm

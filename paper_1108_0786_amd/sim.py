@@ -140,6 +140,10 @@ class BatchSim:
     def step(self, n=1):
         check(self.lib, self.ctx, self.lib.lbm_step(self.ctx, int(n)))
 
+    def prepare(self, n):
+        """Capture the graphs that step(n) replays, without running them."""
+        check(self.lib, self.ctx, self.lib.lbm_prepare(self.ctx, int(n)))
+
     def status(self):
         return check(self.lib, self.ctx, self.lib.lbm_status(self.ctx))
 
@@ -295,10 +299,10 @@ def vacuum_run(cases, steps, traj_cap=0, device="cuda:0"):
                        device=dev) if traj_cap else None
     with torch.cuda.device(dev):
         stream = torch.cuda.current_stream(dev).cuda_stream
-        rc = lib.lbm_vacuum_run(bodies, nb, springs, ns, drives, nd, len(cases), int(steps),
-                                C.c_void_p(traj.data_ptr()) if traj is not None else None, int(traj_cap), out,
-                                C.c_void_p(stream))
+        run = lib.lbm_vacuum_run
+        rc = run(bodies, nb, springs, ns, drives, nd, len(cases), int(steps),
+                 C.c_void_p(traj.data_ptr()) if traj is not None else None, int(traj_cap), out, C.c_void_p(stream))
     if rc != _abi.LBM_OK:
-        raise _abi.LbmError(rc, "lbm_vacuum_run failed")
+        raise _abi.LbmError(rc, f"{run.__name__} failed")
     states = [[_body_dict(out[s * nb + b]) for b in range(nb)] for s in range(len(cases))]
     return states, (traj.cpu().numpy() if traj is not None else None)
