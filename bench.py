@@ -57,14 +57,14 @@ def sweep_bytes(case, n_fluid, storage):
     return n_fluid * 2 * 19 * s + case.ncells
 
 
-def time_leg(case, storage, steps, warmup):
+def time_leg(case, storage, steps, warmup, tune=None):
     import numpy as np
     import torch
 
     from paper_1108_0786_amd.sim import Sim
 
     print(f"[bench] leg {storage}: {case.name}, warmup {warmup}, steps {steps}", file=sys.stderr, flush=True)
-    sim = Sim(case, storage=storage, device="cuda:0", shift_log2=16)
+    sim = Sim(case, storage=storage, device="cuda:0", shift_log2=16, tune=tune)
     n_fluid = int((sim.flags() & 0x7F == 0).sum())
     sim.step(warmup)
     # capture the graphs the timed run replays (nothing runs)

@@ -289,9 +289,19 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *                         launch can be resident at once (up to the device's
  *                         occupancy for it: a few boxes per launch), all
  *                         workgroups of a box share its mapping; 0: one
- *                         workgroup maps each box.  Results are identical. */
+ *                         workgroup maps each box.  Results are identical.
+ *   LBM_TUNE_STREAMING    0 (default): the sweep reads one population buffer
+ *                         and pushes into the other (Eq. streaming as
+ *                         written); 1: it streams in place in one buffer (the
+ *                         "AA" access pattern of Bailey et al. 2009: at even
+ *                         steps every cell reads and writes only its own
+ *                         slots, at odd steps it pulls from and pushes to its
+ *                         neighbours).  Switching converts the current
+ *                         populations between the layouts; results are
+ *                         identical bit for bit.  The adjoint runs the
+ *                         two-buffer sweep either way. */
 enum { LBM_TUNE_BLOCK = 0, LBM_TUNE_XCD_ORDER = 1, LBM_TUNE_GRAPH_STEPS = 2, LBM_TUNE_FULL_REMAP = 3,
-       LBM_TUNE_NONTEMPORAL = 4, LBM_TUNE_COOP_REMAP = 5 };
+       LBM_TUNE_NONTEMPORAL = 4, LBM_TUNE_COOP_REMAP = 5, LBM_TUNE_STREAMING = 6 };
 int lbm_tune(lbm_ctx *ctx, int32_t key, int64_t value);
 
 /* Kernel timing.  With enable = 1, lbm_step launches every kernel itself (no

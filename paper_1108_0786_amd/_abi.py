@@ -11,7 +11,8 @@ LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_OVERLAP, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_
 ERROR_NAMES = {-1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_OVERLAP", -4: "LBM_E_UNSTABLE",
                -5: "LBM_E_STATE", -6: "LBM_E_CAPACITY", -7: "LBM_E_SYNC"}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
-TUNE = {"block": 0, "xcd_order": 1, "graph_steps": 2, "full_remap": 3, "nontemporal": 4, "coop_remap": 5}
+TUNE = {"block": 0, "xcd_order": 1, "graph_steps": 2, "full_remap": 3, "nontemporal": 4, "coop_remap": 5,
+        "streaming": 6}
 TRAJ_DOUBLES = 16
 
 SYMBOLS = [

@@ -181,6 +181,14 @@ struct LinkRec {
 // position, and the exact integer sums of the geometric term 2 w_alpha
 // e_alpha: torque (2 d + 1) x (36 * 2 w_alpha e_alpha), d the integer lever
 // offset, and force 36 * 2 w_alpha e_alpha.
+// One store of a remap in the swapped in-place layout: element `at` of the
+// population array gets `v`.
+struct RelocRec {
+    long long at;
+    double v;
+};
+static_assert(sizeof(LinkRec) == 4 * sizeof(RelocRec), "four relocation records fit one link record");
+
 struct ForceRec {
     double f[3];
     double t[3];
@@ -207,7 +215,8 @@ struct BoxDesc {
     uint8_t *old_owner;        // N bytes: owner before the last remap
     int *link_cell;
     signed char *link_dir, *link_body;
-    LinkRec *link_rec;         // one scratch record per link, written and summed by the sweep
+    LinkRec *link_rec;         // one scratch record per link, written and summed by the sweep; a remap
+                               // in the swapped in-place layout lists its moves here (4 per record)
     ForceRec *frec;            // momentum-exchange sums per (wave, body), by body, written by the sweep
     int *grp_pos;              // record of the wave's q-th body at the wave's first link + q
     int *link_base;            // N ints: first link of a boundary cell
@@ -222,7 +231,7 @@ struct BoxDesc {
     double *flow_sum;          // 3 arrays of N: summed fluid velocity (x, y, z) for the time average, or null
     int *flow_count;           // N: samples in which the cell was fluid
     int flow_every;            // sample the steps n with n % flow_every == 0 (0: none)
-    int pad1;
+    int aa;                    // 1: the populations stream in place in pop0 or pop1 (layout by step parity)
     // mutable state, advanced on the device
     long long step;
     int cur;                   // index of the buffer holding the current populations

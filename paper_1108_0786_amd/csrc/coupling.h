@@ -42,6 +42,8 @@ struct CoupleCtl {
     int counts[kRedBlocks];      // links found in each workgroup's slice of the cell box
     unsigned long long margin[kMaxBodies];  // bits of each body's margin (a non-negative double)
     unsigned owner_changes;      // cells whose owner a mapping has changed, counted since set-up
+    int swapped;                 // published by the first workgroup: the remap sees the swapped layout
+    unsigned reloc_count;        // stores listed by a remap in the swapped layout
 };
 
 struct CoupleShared {
@@ -61,6 +63,7 @@ struct CoupleShared {
     int rcount;                // cells to refill found in the current round
     int rlist[kCoupleThreads];
     int cur;                   // index of the current population buffer
+    int swapped;               // 1: the populations are in the swapped in-place layout (before an odd step)
     // the box's small tables, staged in LDS by the workgroup that finishes the step
     DevBody body[kMaxBodies];
     DevSpring spring[kMaxSprings];
@@ -117,7 +120,7 @@ __device__ __forceinline__ double load_dev(const void *p, size_t i, float inv_sc
 // B is the kernel's snapshot of the descriptor and Bg the descriptor itself:
 // the offsets are read from Bg, as an index into the snapshot's array would
 // move the whole snapshot out of registers.
-__device__ void sum_records(const BoxDesc &B, const BoxDesc &Bg, CoupleShared &sh) {
+__device__ __forceinline__ void sum_records(const BoxDesc &B, const BoxDesc &Bg, CoupleShared &sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int b = wave; b < B.nb; b += kCoupleThreads / 64) {
         const int h0 = min(Bg.rec_off[b], B.link_cap), h1 = min(Bg.rec_off[b + 1], B.link_cap);
@@ -157,7 +160,7 @@ __device__ void sum_records(const BoxDesc &B, const BoxDesc &Bg, CoupleShared &s
 // part, G = (integer sum) / 36 and its torque S / 72 - f x G, f the
 // fractional part of the body position (lever arms are taken from the cell
 // R = floor(X)).  Needs the body table in LDS and sum_records done.
-__device__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
+__device__ __forceinline__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
     const int b = threadIdx.x;
     if (b < B.nb) {
 #pragma clang fp contract(off)
@@ -184,7 +187,7 @@ __device__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
 // ---------------------------------------------------------------------------
 // B is the kernel's snapshot of the box descriptor (read only); the step
 // counter, buffer index and status go to the descriptor itself, Bg.
-__device__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
+__device__ __forceinline__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
     const int nb = B.nb;
     const long long n = B.step;
     const int t = threadIdx.x;
@@ -301,7 +304,7 @@ __device__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
         for (int q = 0; q < nb; ++q) bad |= sh.bad[q];
         if (bad) Bg.status = -4;
         Bg.step = n + 1;
-        sh.cur ^= 1;
+        if (!B.aa) sh.cur ^= 1;   // in-place streaming keeps its one array
         Bg.cur = sh.cur;
     }
     __syncthreads();
@@ -340,7 +343,7 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
 // scan: the union of every body's old and new bounding box plus two cells.
 // Called by the first wave, one lane per body; the lanes combine with wave
 // votes and min / max reductions, which do not depend on the order.
-__device__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool force) {
+__device__ __forceinline__ void decide_map(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, bool force) {
     const int nb = B.nb, b = threadIdx.x;
     bool finite = true, need = false, soon = false;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -432,7 +435,7 @@ __device__ __forceinline__ void map_cell(const MapBox &m, int t, int &i, int &j,
 }
 
 // pass 1: new owners; remember the old ones
-__device__ void map_owners(const BoxDesc &B, const CoupleShared &sh, const MapBox &m, int t0, int t1) {
+__device__ __forceinline__ void map_owners(const BoxDesc &B, const CoupleShared &sh, const MapBox &m, int t0, int t1) {
     const int nb = B.nb, nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
     for (int t = t0 + (int)threadIdx.x; t < t1; t += kCoupleThreads) {
         int i, j, k;
@@ -456,7 +459,7 @@ __device__ void map_owners(const BoxDesc &B, const CoupleShared &sh, const MapBo
 // this thread's part of the margin of body b over the slice: the smallest
 // distance of a scanned cell centre from the body's surface; until the body
 // has moved that far no cell changes side
-__device__ double map_margin(const BoxDesc &B, const DevBody &bd, const MapBox &m, int t0, int t1) {
+__device__ __forceinline__ double map_margin(const BoxDesc &B, const DevBody &bd, const MapBox &m, int t0, int t1) {
     double mm = 1e300;
     for (int t = t0 + (int)threadIdx.x; t < t1; t += kCoupleThreads) {
         int i, j, k;
@@ -469,6 +472,16 @@ __device__ double map_margin(const BoxDesc &B, const DevBody &bd, const MapBox &
     return mm;
 }
 
+// Equilibrium deviation of direction a at density 1 + drho and velocity u
+// (the refill of a cell that left a body), rounding spelled out so that
+// every mapping gives the same bits.
+__device__ __forceinline__ double refill_value(int a, double drho, double rho, const double u[3]) {
+#pragma clang fp contract(off)
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double eu = ex(a) * u[0] + ey(a) * u[1] + ez(a) * u[2];
+    return wgt(a) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+}
+
 // pass 2: refill cells that left a body (equilibrium at the body's velocity,
 // density averaged over neighbours that are fluid before and after); needs
 // pass 1 done on the neighbours.  The cells to refill are gathered first;
@@ -477,7 +490,8 @@ __device__ double map_margin(const BoxDesc &B, const DevBody &bd, const MapBox &
 // the order one thread would take (directions ascending), so the result
 // does not depend on the gathering order.
 template <typename S>
-__device__ void map_refill(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int cur) {
+__device__ __forceinline__ void map_refill(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int cur) {
+    if (sh.swapped) return;   // map_swap_gather refilled
     const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
     void *popc = cur ? B.pop1 : B.pop0;
     const size_t stride = (size_t)B.stride;
@@ -532,21 +546,146 @@ __device__ void map_refill(const BoxDesc &B, CoupleShared &sh, const MapBox &m, 
             int d[3];
             lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
             wall_velocity(bd, r, u);
-            const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
             if (lane < 19) {
-                const int a = lane;
-                const double eu = ex(a) * u[0] + ey(a) * u[1] + ez(a) * u[2];
-                const double v = wgt(a) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
-                Storage<S>::store((S *)popc, (size_t)a * stride + c, (typename Storage<S>::C)v, B.scale);
+                const double v = refill_value(lane, drho, rho, u);
+                Storage<S>::store((S *)popc, (size_t)lane * stride + c, (typename Storage<S>::C)v, B.scale);
             }
         }
+    }
+}
+
+// Pass 2 in the swapped layout of in-place streaming (the populations
+// before an odd step).  There f_b(x) sits at slot opp(b) of x - e_b when
+// that neighbour is fluid, else at slot b of x, so a cell that changes side
+// moves its neighbours' populations as well:
+//   c uncovered (body -> fluid), x = c + e_b fluid before and after:
+//     f_b(x) moves from slot b of x to slot opp(b) of c;
+//   c covered (fluid -> body), x likewise:
+//     f_b(x), which c pushed at the last step, moves from slot opp(b) of c to
+//     slot b of x;
+// and the refill of an uncovered cell goes to the slots its new neighbours
+// give it.  Some of these stores land where other moves or refills read
+// (the slot a move of c empties is where c's own refill of the opposite
+// direction goes), so every value is read first and listed (gather, into
+// the link-record scratch, which the momentum exchange has consumed by now),
+// and the list is stored after a barrier (scatter); no two stores share a
+// slot.  The values and the refill arithmetic are those of the own layout,
+// so both layouts map bit for bit alike.
+__device__ __forceinline__ bool in_map(const MapBox &m, int i, int j, int k) {
+    return i >= m.lo[0] && i < m.lo[0] + m.bx && j >= m.lo[1] && j < m.lo[1] + m.by && k >= m.lo[2] &&
+           m.bx > 0 && m.by > 0 && k < m.lo[2] + m.ncell / (m.bx * m.by);
+}
+
+// fluid before this mapping (old_owner is only written inside the box)
+__device__ __forceinline__ bool fluid_before(const BoxDesc &B, const MapBox &m, int c, int i, int j, int k) {
+    return in_map(m, i, j, k) ? B.old_owner[c] == 0 : (B.flags[c] & kOwnerMask) == 0;
+}
+
+// element of f_b(x) in the swapped layout; before == true: under the flags
+// before this mapping, else under the new ones
+__device__ __forceinline__ size_t swapped_slot(const BoxDesc &B, const MapBox &m, int b, int c, int i, int j, int k,
+                                               bool before) {
+    const size_t stride = (size_t)B.stride;
+    if (b == 0) return (size_t)c;
+    int ti, tj, tk;
+    if (neighbour_rt(opp(b), i, j, k, B.nx, B.ny, B.nz, B.per, ti, tj, tk)) {
+        const int s = ti + B.nx * (tj + B.ny * tk);
+        const bool fl = before ? fluid_before(B, m, s, ti, tj, tk) : (B.flags[s] & kOwnerMask) == 0;
+        if (fl) return (size_t)opp(b) * stride + (size_t)s;
+    }
+    return (size_t)b * stride + (size_t)c;
+}
+
+__device__ __forceinline__ void reloc_push(const BoxDesc &B, BoxDesc &Bg, CoupleCtl *ctl, size_t at, double v) {
+    const unsigned e = atomicAdd(&ctl->reloc_count, 1u);
+    if (e < 4u * (unsigned)B.link_cap) {
+        RelocRec r;
+        r.at = (long long)at;
+        r.v = v;
+        ((RelocRec *)B.link_rec)[e] = r;
+    } else {
+        Bg.status = -6;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void map_swap_gather(const BoxDesc &B, BoxDesc &Bg, const CoupleShared &sh, const MapBox &m, int t0,
+                                int t1, int cur, CoupleCtl *ctl) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
+    const void *pop = cur ? B.pop1 : B.pop0;
+    const size_t stride = (size_t)B.stride;
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kCoupleThreads) {
+        int i, j, k;
+        map_cell(m, t, i, j, k);
+        const int c = i + nx * (j + ny * k);
+        if (c < 0 || c >= B.N) continue;
+        const bool was = B.old_owner[c] == 0, is = (B.flags[c] & kOwnerMask) == 0;
+        if (was == is) continue;
+        // loops kept rolled: this runs only at remaps, and the coupling
+        // kernel must stay within its registers
+#pragma unroll 1
+        for (int b = 1; b < 19; ++b) {
+            int ti, tj, tk;
+            if (!neighbour_rt(b, i, j, k, nx, ny, nz, per, ti, tj, tk)) continue;
+            const int x = ti + nx * (tj + ny * tk);
+            if (!fluid_before(B, m, x, ti, tj, tk) || (B.flags[x] & kOwnerMask) != 0) continue;
+            const size_t from = is ? (size_t)b * stride + x : (size_t)opp(b) * stride + c;
+            const size_t to = is ? (size_t)opp(b) * stride + c : (size_t)b * stride + x;
+            reloc_push(B, Bg, ctl, to, load_dev<S>(pop, from, B.inv_scale));
+        }
+        if (!is) continue;
+        // refill: density averaged over the neighbours that are fluid before
+        // and after (each neighbour's populations summed in direction order,
+        // the neighbours added in direction order), as in map_refill
+        double total = 0.0;
+        int count = 0;
+#pragma unroll 1
+        for (int a = 1; a < 19; ++a) {
+            int ti, tj, tk;
+            if (!neighbour_rt(a, i, j, k, nx, ny, nz, per, ti, tj, tk)) continue;
+            const int nc = ti + nx * (tj + ny * tk);
+            if (!fluid_before(B, m, nc, ti, tj, tk) || (B.flags[nc] & kOwnerMask) != 0) continue;
+            double sum = load_dev<S>(pop, (size_t)nc, B.inv_scale);
+#pragma unroll 1
+            for (int q = 1; q < 19; ++q)
+                sum = sum + load_dev<S>(pop, swapped_slot(B, m, q, nc, ti, tj, tk, true), B.inv_scale);
+            total = total + sum;
+            ++count;
+        }
+        const double drho = count ? total / (double)count : 0.0;
+        const double rho = 1.0 + drho;
+        const DevBody &bd = sh.body[B.old_owner[c] - 1];
+        double r[3], u[3];
+        int d[3];
+        lever_arm(bd, i, j, k, nx, ny, nz, per, r, d);
+        wall_velocity(bd, r, u);
+#pragma unroll 1
+        for (int a = 0; a < 19; ++a)
+            reloc_push(B, Bg, ctl, swapped_slot(B, m, a, c, i, j, k, false), refill_value(a, drho, rho, u));
+    }
+}
+
+// Store the listed values: workgroup `part` of `parts` takes one slice.
+template <typename S>
+__device__ __forceinline__ void map_swap_scatter(const BoxDesc &B, int cur, CoupleCtl *ctl, int part, int parts) {
+    void *pop = cur ? B.pop1 : B.pop0;
+    const int n = (int)min(__hip_atomic_load(&ctl->reloc_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           4u * (unsigned)B.link_cap);
+    const int chunk = (n + parts - 1) / parts;
+    const int e0 = min(part * chunk, n), e1 = min(e0 + chunk, n);
+    const RelocRec *list = (const RelocRec *)B.link_rec;
+    const size_t lim = (size_t)19 * (size_t)B.stride;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kCoupleThreads) {
+        const RelocRec r = list[e];
+        if (r.at >= 0 && (size_t)r.at < lim)
+            Storage<S>::store((S *)pop, (size_t)r.at, (typename Storage<S>::C)r.v, B.scale);
     }
 }
 
 // pass 3: near-body marks and boundary links of the slice, in cell order,
 // numbered from `first`; needs pass 1 done on the neighbours.  With
 // write = false only counts.  Returns the number of links in the slice.
-__device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int first,
+__device__ __forceinline__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, int t0, int t1, int first,
                          bool write) {
     const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
     int running = first;
@@ -619,7 +758,7 @@ __device__ int map_links(const BoxDesc &B, CoupleShared &sh, const MapBox &m, in
 // are the wave's own).  Thread t takes a contiguous range of links and the
 // waves that start in it; one block scan per body numbers the records.
 // Needs the whole link list written.
-__device__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int L) {
+__device__ __forceinline__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int L) {
     const int chunk = (L + kCoupleThreads - 1) / kCoupleThreads;
     const int l0 = min((int)threadIdx.x * chunk, L), l1 = min(l0 + chunk, L);
     auto wave_mask = [&](int l, int w) {
@@ -660,7 +799,7 @@ __device__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int 
 
 // Record the positions and orientations the mapping used (the remap skip
 // measures motion from them).
-__device__ void map_record(const BoxDesc &B, const CoupleShared &sh, double *qmaps) {
+__device__ __forceinline__ void map_record(const BoxDesc &B, const CoupleShared &sh, double *qmaps) {
     const int b = threadIdx.x;
     if (b < B.nb) {
         for (int q = 0; q < 3; ++q) B.bodies[b].Xmap[q] = sh.body[b].anchor[q] + sh.body[b].D[q];
@@ -670,17 +809,25 @@ __device__ void map_record(const BoxDesc &B, const CoupleShared &sh, double *qma
 
 // The whole mapping by one workgroup.
 template <typename S>
-__device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, double *qmaps, double *margins) {
+__device__ __forceinline__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, double *qmaps, double *margins) {
     const MapBox m = map_box(sh);
+    CoupleCtl *ctl = (CoupleCtl *)B.ctl;
+    if (threadIdx.x == 0) ctl->reloc_count = 0u;
     map_owners(B, sh, m, 0, m.ncell);
     for (int b = 0; b < B.nb; ++b) {
         const double mm = block_min(map_margin(B, sh.body[b], m, 0, m.ncell), sh);
         if (threadIdx.x == 0) margins[b] = mm;
     }
     map_record(B, sh, qmaps);
-    __threadfence_block();
+    __threadfence();
     __syncthreads();
-    map_refill<S>(B, sh, m, 0, m.ncell, sh.cur);
+    if (sh.swapped) {
+        map_swap_gather<S>(B, Bg, sh, m, 0, m.ncell, sh.cur, ctl);
+        __threadfence();
+        __syncthreads();
+        map_swap_scatter<S>(B, sh.cur, ctl, 0, 1);
+    }
+    map_refill<S>(B, sh, m, 0, m.ncell, sh.cur);   // nothing to do in the swapped layout
     __threadfence_block();
     __syncthreads();
     const int total = map_links(B, sh, m, 0, m.ncell, 0, true);
@@ -700,7 +847,7 @@ __device__ void remap_box(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, doubl
 // Waiting workgroups poll with plain device-coherent loads and take one
 // acquire fence at the end: an acquire on every poll would invalidate their
 // L2 over and over, slowing the workgroup that everyone waits for.
-__device__ bool box_barrier(CoupleCtl *ctl, CoupleShared &sh, BoxDesc &Bg) {
+__device__ __forceinline__ bool box_barrier(CoupleCtl *ctl, CoupleShared &sh, BoxDesc &Bg) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this thread's stores visible device-wide
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -735,7 +882,7 @@ __device__ bool box_barrier(CoupleCtl *ctl, CoupleShared &sh, BoxDesc &Bg) {
 // links from the sum of the counts before it: the list comes out in the same
 // cell order, and every result bit for bit the same, as with one workgroup.
 template <typename S>
-__device__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, CoupleCtl *ctl, int r, double *qmaps,
+__device__ __forceinline__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, CoupleCtl *ctl, int r, double *qmaps,
                            double *margins) {
     const MapBox m = map_box(sh);
     const int chunk = (m.ncell + kRedBlocks - 1) / kRedBlocks;
@@ -753,7 +900,12 @@ __device__ void remap_coop(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, Coup
     if (r == 0 && (int)threadIdx.x < B.nb)
         margins[threadIdx.x] = __longlong_as_double(
             (long long)__hip_atomic_load(&ctl->margin[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    map_refill<S>(B, sh, m, t0, t1, sh.cur);
+    if (sh.swapped) {
+        map_swap_gather<S>(B, Bg, sh, m, t0, t1, sh.cur, ctl);
+        if (!box_barrier(ctl, sh, Bg)) return;
+        map_swap_scatter<S>(B, sh.cur, ctl, r, kRedBlocks);
+    }
+    map_refill<S>(B, sh, m, t0, t1, sh.cur);   // nothing to do in the swapped layout
     const int mine = map_links(B, sh, m, t0, t1, 0, false);
     if (threadIdx.x == 0) __hip_atomic_store(&ctl->counts[r], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!box_barrier(ctl, sh, Bg)) return;
@@ -845,7 +997,7 @@ __device__ __forceinline__ void stage_store(const BoxDesc &B, CoupleShared &sh, 
     __syncthreads();
 }
 
-__device__ void stage_out(const BoxDesc &B, CoupleShared &sh) {
+__device__ __forceinline__ void stage_out(const BoxDesc &B, CoupleShared &sh) {
     __syncthreads();
     copy_words(B.bodies, sh.body, (int)sizeof(DevBody) * B.nb);
     __threadfence_block();
@@ -887,7 +1039,12 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     const bool lead = r == 0;
     if (!share && !lead) return;
     if (lead) {
-        if (threadIdx.x == 0) sh.cur = B.cur;
+        if (threadIdx.x == 0) {
+            sh.cur = B.cur;
+            // in-place streaming: the layout the mapping sees is that of the
+            // next step, n + 1 after a step
+            sh.swapped = B.aa && ((B.step + (mode == kModeStep ? 1 : 0)) & 1) != 0;
+        }
         Staged st;
         stage_load(B, sh, qm, mg, st);
         if (mode == kModeStep) sum_records(B, Bg, sh);
@@ -910,6 +1067,8 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         if (threadIdx.x == 0) {
             ctl->map_req = sh.map_req;
             ctl->cur = sh.cur;
+            ctl->swapped = sh.swapped;
+            ctl->reloc_count = 0u;
             for (int q = 0; q < 3; ++q) {
                 ctl->lo[q] = sh.lo[q];
                 ctl->hi[q] = sh.hi[q];
@@ -922,6 +1081,7 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     if (threadIdx.x == 0) {
         sh.map_req = __hip_atomic_load(&ctl->map_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sh.cur = __hip_atomic_load(&ctl->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.swapped = __hip_atomic_load(&ctl->swapped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int q = 0; q < 3; ++q) {
             sh.lo[q] = __hip_atomic_load(&ctl->lo[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             sh.hi[q] = __hip_atomic_load(&ctl->hi[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -16,7 +16,7 @@
 #include "common.h"
 #include "adjoint.h"
 #include "coupling.h"
-#include "sweep.h"
+#include "sweep_aa.h"
 
 using namespace lbm;
 
@@ -68,6 +68,7 @@ struct lbm_ctx {
     bool work_dirty = true;
     bool force_map = false;
     bool coop_remap = true;        // share the mapping among a box's coupling workgroups
+    bool aa = false;               // stream in place (one buffer, layout by step parity)
     bool flow_any = false;         // some box samples the time-averaged flow
     int coop_blocks = 0;           // coupling workgroups that are surely resident at once
     bool poisoned = false;
@@ -146,7 +147,7 @@ int validate_params(lbm_ctx *c, const lbm_params &p) {
     return LBM_OK;
 }
 
-BoxDesc make_desc(const HostBox &h, int storage) {
+BoxDesc make_desc(const HostBox &h, int storage, bool aa) {
     BoxDesc d;
     memset(&d, 0, sizeof(d));
     d.nx = h.p.nx;
@@ -185,13 +186,14 @@ BoxDesc make_desc(const HostBox &h, int storage) {
     d.flow_sum = h.flow_sum;
     d.flow_count = h.flow_count;
     d.flow_every = h.flow_every;
+    d.aa = aa ? 1 : 0;
     return d;
 }
 
 // Upload the static fields of a box descriptor without touching the mutable
 // device state (step, cur, link_count, status).
 int upload_desc(lbm_ctx *c, int b) {
-    BoxDesc d = make_desc(c->boxes[b], c->storage);
+    BoxDesc d = make_desc(c->boxes[b], c->storage, c->aa);
     const size_t static_bytes = offsetof(BoxDesc, step);
     HIP_TRY(c, hipMemcpyAsync(c->d_boxes + b, &d, static_bytes, hipMemcpyHostToDevice, c->stream));
     return LBM_OK;
@@ -464,6 +466,15 @@ int rebuild_work(lbm_ctx *c) {
 
 template <typename S, int BLOCK, bool FLOW>
 int launch_sweep_f(lbm_ctx *c) {
+    if (c->aa) {
+        if (c->nontemporal)
+            hipLaunchKernelGGL((sweep_aa_kernel<S, BLOCK, true, FLOW>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
+                               c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+        else
+            hipLaunchKernelGGL((sweep_aa_kernel<S, BLOCK, false, FLOW>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
+                               c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+        return LBM_OK;
+    }
     if (c->nontemporal)
         hipLaunchKernelGGL((sweep_kernel<S, BLOCK, true, FLOW>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
                            c->d_boxes, c->d_work, c->nwork, c->xcd_order);
@@ -631,8 +642,9 @@ __global__ void export_kernel(const BoxDesc *boxes, int bi, double *dst) {
     if (idx >= 19 * N) return;
     const size_t a = idx / N, cell = idx % N;
     const S *src = (const S *)(B.cur ? B.pop1 : B.pop0);
-    dst[idx] = (B.flags[cell] & kOwnerMask) ? 0.0
-                                            : (double)Storage<S>::load(src, a * B.stride + cell, B.inv_scale);
+    dst[idx] = (B.flags[cell] & kOwnerMask)
+                   ? 0.0
+                   : (double)Storage<S>::load(src, current_slot(B, swapped_now(B), (int)a, (int)cell), B.inv_scale);
 }
 
 template <typename S>
@@ -645,7 +657,10 @@ __global__ void export_cells_kernel(const BoxDesc *boxes, int bi, const int *cel
     const bool ok = c >= 0 && c < B.N;
     for (int a = 0; a < 19; ++a) {
         double v = __longlong_as_double(0x7ff8000000000000LL);
-        if (ok) v = (B.flags[c] & kOwnerMask) ? 0.0 : (double)Storage<S>::load(src, (size_t)a * B.stride + c, B.inv_scale);
+        if (ok)
+            v = (B.flags[c] & kOwnerMask)
+                    ? 0.0
+                    : (double)Storage<S>::load(src, current_slot(B, swapped_now(B), a, c), B.inv_scale);
         dst[(size_t)a * n + m] = v;
     }
 }
@@ -658,7 +673,27 @@ __global__ void import_kernel(const BoxDesc *boxes, int bi, const double *srcd) 
     if (idx >= 19 * N) return;
     const size_t a = idx / N, cell = idx % N;
     S *dst = (S *)(B.cur ? B.pop1 : B.pop0);
-    Storage<S>::store(dst, a * B.stride + cell, (typename Storage<S>::C)srcd[idx], B.scale);
+    // body cells have no slots of their own in the swapped layout
+    if (swapped_now(B) && (B.flags[cell] & kOwnerMask)) return;
+    Storage<S>::store(dst, current_slot(B, swapped_now(B), (int)a, (int)cell), (typename Storage<S>::C)srcd[idx],
+                      B.scale);
+}
+
+// Copy the populations of box bi from buffer `from` in one layout to buffer
+// `to` in the other (swapped: the swapped in-place layout, else own slots);
+// fluid cells only.
+template <typename S>
+__global__ void relayout_kernel(const BoxDesc *boxes, int bi, int from, int to, int from_swapped, int to_swapped) {
+    const BoxDesc &B = boxes[bi];
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t N = (size_t)B.N;
+    if (idx >= 19 * N) return;
+    const int a = (int)(idx / N), cell = (int)(idx % N);
+    if (B.flags[cell] & kOwnerMask) return;
+    const S *src = (const S *)(from ? B.pop1 : B.pop0);
+    S *dst = (S *)(to ? B.pop1 : B.pop0);
+    const auto v = Storage<S>::load(src, current_slot(B, from_swapped != 0, a, cell), B.inv_scale);
+    Storage<S>::store(dst, current_slot(B, to_swapped != 0, a, cell), v, B.scale);
 }
 
 // Plain streaming copy: each thread moves four 16-byte vectors per round with
@@ -720,6 +755,46 @@ __global__ void save_hist_kernel(const BoxDesc *boxes, BodyHist *out) {
         out[b].O[q] = d.O[q];
     }
     for (int q = 0; q < 4; ++q) out[b].q[q] = d.q[q];
+}
+
+__global__ void set_layout_kernel(BoxDesc *boxes, int bi, int cur, int aa) {
+    boxes[bi].cur = cur;
+    boxes[bi].aa = aa;
+}
+
+// Switch every box between the two-buffer and the in-place sweep: the
+// populations go to the other buffer in the layout of the new mode at the
+// box's present step (no copy where both layouts agree).  Graphs captured
+// for the old mode are dropped by the caller where needed.
+int set_streaming(lbm_ctx *c, bool aa) {
+    if (aa == c->aa) return LBM_OK;
+    const int nbox = (int)c->boxes.size();
+    std::vector<BoxDesc> d(nbox);
+    int rc = copy_sync(c, d.data(), c->d_boxes, sizeof(BoxDesc) * nbox, hipMemcpyDeviceToHost);
+    if (rc) return rc;
+    for (int b = 0; b < nbox; ++b) {
+        const bool odd = (d[b].step & 1) != 0;
+        const bool from_swapped = c->aa && odd, to_swapped = aa && odd;
+        int cur = d[b].cur;
+        if (from_swapped != to_swapped) {
+            const size_t n = (size_t)19 * c->boxes[b].N;
+            const unsigned blocks = (unsigned)((n + 255) / 256);
+            rc = dispatch_storage(c->storage, [&](auto *tag) -> int {
+                using S = std::remove_pointer_t<decltype(tag)>;
+                hipLaunchKernelGGL(relayout_kernel<S>, dim3(blocks), dim3(256), 0, c->stream, c->d_boxes, b, cur,
+                                   cur ^ 1, from_swapped ? 1 : 0, to_swapped ? 1 : 0);
+                return LBM_OK;
+            });
+            if (rc) return rc;
+            cur ^= 1;
+        }
+        hipLaunchKernelGGL(set_layout_kernel, dim3(1), dim3(1), 0, c->stream, c->d_boxes, b, cur, aa ? 1 : 0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("relayout: ") + hipGetErrorString(e));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->aa = aa;
+    return LBM_OK;
 }
 
 __global__ void set_state_kernel(BoxDesc *boxes, long long step, int cur) {
@@ -939,10 +1014,18 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
     if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
     if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
     if (c->flow_any) return fail(c, LBM_E_STATE, "stop the flow average before the adjoint (its recomputation would sample)");
-    return dispatch_storage(c->storage, [&](auto *tag) -> int {
+    // the reverse pass keeps and replays its states in the two-buffer layout
+    const bool was_aa = c->aa;
+    if (was_aa && (rc = set_streaming(c, false))) return rc;
+    rc = dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         return adjoint_impl<S>(c, nsteps, checkpoint_every, dJ_ddisp, J, grad);
     });
+    if (was_aa) {
+        const int back = set_streaming(c, true);
+        if (!rc) rc = back;
+    }
+    return rc;
 }
 
 int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
@@ -1394,6 +1477,10 @@ int lbm_tune(lbm_ctx *c, int32_t key, int64_t value) {
         case LBM_TUNE_COOP_REMAP:
             if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "cooperative remap is 0 or 1");
             c->coop_remap = value != 0;
+            break;
+        case LBM_TUNE_STREAMING:
+            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "streaming is 0 (two buffers) or 1 (in place)");
+            if ((rc = set_streaming(c, value != 0))) return rc;
             break;
         default:
             return fail(c, LBM_E_ARG, "unknown tuning key");

@@ -104,68 +104,57 @@ struct PushAll<S, 19> {
 
 // Momentum exchange of the wave's near-body cells (Eq. hydroF), body by
 // body.  Called by every lane of a wave that holds at least one near-body
-// cell, after the pushes: lane l adds the scratch records of its own links
-// into body b (links first .. first + n - 1 of its cell, in direction
-// order), the wave adds the lanes in a fixed xor-shuffle tree, and lane 0
-// writes the sums to the record that the mapping reserved for (this wave,
-// body b): record grp_pos[l0 + q] for the wave's q-th body in ascending
-// order, l0 being the wave's first link.  A wave covers 64 consecutive
-// cells of its box however the sweep is launched, so the sums come out the
-// same bit for bit.  The populations are no longer live here, which keeps
-// the sweep within its register budget.
-// The owners of the cell's neighbours are loaded again here (they were
-// loaded for the pushes moments ago) rather than kept through the pushes.
-__device__ __forceinline__ void body_links(const BoxDesc &B, bool near, int cell, int i, int j, int k) {
-    unsigned lm = 0;
-    int n = 0, first = 0x7fffffff;
-    if (near) {
-        Owners owner;
-        neighbour_owners(B, cell, i, j, k, owner);
-#pragma unroll
-        for (int a = 1; a < 19; ++a) {
-            const int o = owner.get(a);
-            lm |= o ? 1u << (o - 1) : 0u;
-            n += o ? 1 : 0;
-        }
-        first = B.link_base[cell];
-    }
-    unsigned wm = lm;
-    int l0 = first;
+// cell, after the pushes, with the cell's links [lfirst, lend) (an empty
+// range elsewhere).  A wave covers 64 consecutive cells of its box, and the
+// links are numbered in cell order, so the wave's links are one contiguous
+// range [l0, l1): lane q takes links l0 + q, l0 + q + 64, ... (coalesced
+// loads of the scratch records, a pass or two), the wave adds the lanes in
+// a fixed xor-shuffle tree, and lane 0 writes the sums to the record that
+// the mapping reserved for (this wave, body b): record grp_pos[l0 + n] for
+// the wave's n-th body in ascending order.  The sums come out the same bit
+// for bit however the sweep is launched.  The populations are no longer
+// live here, which keeps the sweep within its register budget.
+__device__ __forceinline__ void body_links(const BoxDesc &B, int lfirst, int lend) {
+    int l0 = lfirst, l1 = lend;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        wm |= __shfl_xor(wm, o, 64);
         l0 = min(l0, __shfl_xor(l0, o, 64));
+        l1 = max(l1, __shfl_xor(l1, o, 64));
     }
-    wm = __builtin_amdgcn_readfirstlane(wm);
     l0 = __builtin_amdgcn_readfirstlane(l0);
+    l1 = min(__builtin_amdgcn_readfirstlane(l1), B.link_cap);
+    if (l0 >= l1) return;
+    const int lane = (int)threadIdx.x & 63;
+    unsigned wm = 0;
+    for (int l = l0 + lane; l < l1; l += 64) wm |= 1u << B.link_body[l];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wm |= __shfl_xor(wm, o, 64);
+    wm = __builtin_amdgcn_readfirstlane(wm);
     for (int q = 0; wm; ++q) {
         const int b = __builtin_ctz(wm);
         wm &= wm - 1;
         double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int ia[6] = {0, 0, 0, 0, 0, 0};
-        if (lm & (1u << b)) {
-#pragma unroll 1
-            for (int l = first; l < first + n && l < B.link_cap; ++l) {
-                if (B.link_body[l] != b) continue;
-                const LinkRec rec = B.link_rec[l];
-                const int cw = two_w36(rec.a);
+        for (int l = l0 + lane; l < l1; l += 64) {
+            if (B.link_body[l] != b) continue;
+            const LinkRec rec = B.link_rec[l];
+            const int cw = two_w36(rec.a);
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    acc[v] += rec.f[v];
-                    acc[3 + v] += rec.t[v];
-                    ia[v] += rec.s[v];
-                }
-                ia[3] += ex(rec.a) * cw;
-                ia[4] += ey(rec.a) * cw;
-                ia[5] += ez(rec.a) * cw;
+            for (int v = 0; v < 3; ++v) {
+                acc[v] += rec.f[v];
+                acc[3 + v] += rec.t[v];
+                ia[v] += rec.s[v];
             }
+            ia[3] += ex(rec.a) * cw;
+            ia[4] += ey(rec.a) * cw;
+            ia[5] += ez(rec.a) * cw;
         }
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             acc[v] = wave_sum(acc[v]);
             ia[v] = wave_sum_int(ia[v]);
         }
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
             const int l = l0 + q;
             if (l < B.link_cap) {
                 const int pos = B.grp_pos[l];
@@ -455,6 +444,7 @@ void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
     const bool general = valid && fluid && !fast;
     const bool near = general && (fl & kNearBit);
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
+    int lfirst = 0x7fffffff, lend = -1;   // this cell's links
     if (general) {
         St::store(gdst, (size_t)cell, f[0], B.scale);
         Owners owner;
@@ -462,10 +452,12 @@ void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
         if (near) {
             neighbour_owners(B, cell, i, j, k, owner);
             slot = B.link_base[cell];
+            lfirst = slot;
         }
         PushAll<S, 1>::run(B, gdst, stride, cell, i, j, k, owner, f, rho, slot);
+        if (near) lend = slot;
     }
-    if (__any(near)) body_links(B, near, cell, i, j, k);
+    if (__any(near)) body_links(B, lfirst, lend);
 }
 
 }  // namespace lbm
