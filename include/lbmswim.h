@@ -290,9 +290,11 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *                         occupancy for it: a few boxes per launch), all
  *                         workgroups of a box share its mapping; 0: one
  *                         workgroup maps each box.  Results are identical.
- *   LBM_TUNE_STREAMING    0 (default): the sweep reads one population buffer
- *                         and pushes into the other (Eq. streaming as
- *                         written); 1: it streams in place in one buffer (the
+ *   LBM_TUNE_STREAMING    0: the sweep reads one population buffer and
+ *                         pushes into the other (Eq. streaming as written;
+ *                         default for LBM_F64, LBM_F16S, LBM_BF16S); 1
+ *                         (default for LBM_F32): it streams in place in one
+ *                         buffer (the
  *                         "AA" access pattern of Bailey et al. 2009: at even
  *                         steps every cell reads and writes only its own
  *                         slots, at odd steps it pulls from and pushes to its

@@ -49,7 +49,7 @@ def test_in_place_matches_two_buffer_bitwise(storage, coop):
     steps = 160
     case = W.forced_motion(steps=steps, storage=storage)
     print(f"[gpu] in-place vs two-buffer, {storage}, coop {coop}", flush=True)
-    ref = _sim(case, storage=storage, traj_cap=steps, tune={"coop_remap": coop})
+    ref = _sim(case, storage=storage, traj_cap=steps, tune={"coop_remap": coop, "streaming": 0})
     aa = _sim(case, storage=storage, traj_cap=steps, tune={"coop_remap": coop, "streaming": 1})
     flags0 = aa.flags()
     odd_changes = even_changes = 0
@@ -109,9 +109,9 @@ def test_switching_mode_mid_run():
     steps = 33
     case = W.forced_motion(steps=steps)
     print("[gpu] streaming mode switched mid-run", flush=True)
-    ref = _sim(case, storage="f64", traj_cap=steps)
+    ref = _sim(case, storage="f64", traj_cap=steps, tune={"streaming": 0})
     ref.step(steps)
-    sw = _sim(case, storage="f64", traj_cap=steps)
+    sw = _sim(case, storage="f64", traj_cap=steps, tune={"streaming": 0})
     sw.step(7)
     sw.tune("streaming", 1)
     sw.step(14)
