@@ -338,6 +338,27 @@ int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs
                    const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
                    int64_t traj_cap, lbm_body *out, void *stream);
 
+/* Bytes of the per-GPU array that lbm_vacuum_run_noalloc keeps its device
+ * tables in. */
+#define LBM_NOALLOC_SCRATCH_BYTES (1 << 20)
+
+/* lbm_vacuum_run for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, run and results, with no hipMalloc or hipFree.  The
+ * device tables of the nsys systems (bodies, springs, drives and one
+ * descriptor per system: 256 nb + 32 ns + 56 nd + 320 bytes per system, each
+ * of the four tables padded to 256 bytes) go into an array of
+ * LBM_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends (860 systems of three beads, two springs and one
+ * drive fit); the caller still owns traj and out.  LBM_E_ARG when the
+ * tables do not fit, or for the argument errors of lbm_vacuum_run.  Every
+ * call on one GPU uses that GPU's array, so calls that overlap in time on
+ * one GPU race; the call writes every table before it runs, and nothing of
+ * an earlier call carries over.  Synchronising. */
+int lbm_vacuum_run_noalloc(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
+                           const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
+                           int64_t traj_cap, lbm_body *out, void *stream);
+
 /* Measurement aid, not part of the method: copy `bytes` bytes (a multiple
  * of 16) from device memory src to device memory dst with a plain streaming
  * kernel on `stream` (hipStream_t): with blocks_per_cu = 0 one 16-byte vector

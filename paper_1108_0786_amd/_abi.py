@@ -20,7 +20,7 @@ SYMBOLS = [
     "lbm_step", "lbm_prepare", "lbm_body_forces", "lbm_body_forces_box", "lbm_get_bodies", "lbm_get_bodies_box",
     "lbm_get_links", "lbm_export_populations", "lbm_export_cells", "lbm_import_populations",
     "lbm_flow_average_begin", "lbm_flow_average_get", "lbm_step_count",
-    "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_vacuum_run",
+    "lbm_status", "lbm_adjoint", "lbm_tune", "lbm_set_timing", "lbm_get_timing", "lbm_vacuum_run", "lbm_vacuum_run_noalloc",
     "lbm_copy_kernel", "lbm_stream_copy", "lbm_struct_sizes", "lbm_last_error", "lbm_destroy",
 ]
 
@@ -99,6 +99,8 @@ def load():
         "lbm_get_timing": ([ctx_p, P(C.c_double), P(C.c_int64)], C.c_int),
         "lbm_vacuum_run": ([P(LbmBody), C.c_int32, P(LbmSpring), C.c_int32, P(LbmDrive), C.c_int32, C.c_int32,
                             C.c_int64, C.c_void_p, C.c_int64, P(LbmBody), C.c_void_p], C.c_int),
+        "lbm_vacuum_run_noalloc": ([P(LbmBody), C.c_int32, P(LbmSpring), C.c_int32, P(LbmDrive), C.c_int32,
+                                    C.c_int32, C.c_int64, C.c_void_p, C.c_int64, P(LbmBody), C.c_void_p], C.c_int),
         "lbm_copy_kernel": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
         "lbm_stream_copy": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_void_p],
                             C.c_int),

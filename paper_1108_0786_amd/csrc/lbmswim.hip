@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1006,6 +1007,51 @@ BoxDesc vacuum_desc(int s, int nb, int ns, int nd, DevBody *bodies, DevSpring *s
     return d;
 }
 
+// Device tables of the allocation-free integrator-only run: one array on
+// every GPU the library runs on, held until the process ends.  Host code
+// uses the address hipGetSymbolAddress returns on the current device, never
+// the array's name.
+constexpr size_t kNoAllocScratch = (size_t)1 << 20;
+static_assert(kNoAllocScratch == LBM_NOALLOC_SCRATCH_BYTES, "header and library agree on the scratch size");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex scratch_mutex;
+std::vector<void *> scratch_addr;   // by device ordinal, filled on the first call on that device
+
+// The current device's address of `scratch`, looked up once per device.
+int scratch_on_current_device(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return LBM_E_HIP;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if ((int)scratch_addr.size() <= dev) scratch_addr.resize(dev + 1, nullptr);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_E_HIP;
+        scratch_addr[dev] = p;
+    }
+    *out = scratch_addr[dev];
+    return LBM_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Copy n records of type D converted from the host array src by `conv` to
+// the device array dst, through a buffer on the stack (a few records at a
+// time, each copy waited for before the buffer is reused).
+template <typename D, typename H, typename Conv>
+int stage_records(D *dst, const H *src, size_t n, Conv conv, hipStream_t st) {
+    constexpr size_t kChunk = 16;
+    D buf[kChunk];
+    for (size_t q0 = 0; q0 < n; q0 += kChunk) {
+        const size_t m = std::min(kChunk, n - q0);
+        for (size_t q = 0; q < m; ++q) buf[q] = conv(src[q0 + q]);
+        if (hipMemcpyAsync(dst + q0, buf, sizeof(D) * m, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return LBM_E_HIP;
+    }
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1083,6 +1129,66 @@ int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs
     (void)hipFree(g_springs);
     (void)hipFree(g_drives);
     (void)hipFree(g_desc);
+    return rc;
+}
+
+int lbm_vacuum_run_noalloc(const lbm_body *bodies, int32_t nb, const lbm_spring *springs, int32_t ns,
+                           const lbm_drive *drives, int32_t nd, int32_t nsys, int64_t nsteps, double *traj,
+                           int64_t traj_cap, lbm_body *out, void *stream) {
+    if (int rc = validate_vacuum(bodies, nb, springs, ns, drives, nd, nsys, nsteps, traj, traj_cap)) return rc;
+    const size_t nbod = (size_t)nsys * nb, nspr = (size_t)nsys * ns, ndrv = (size_t)nsys * nd;
+    const size_t off_spr = align256(sizeof(DevBody) * nbod);
+    const size_t off_drv = off_spr + align256(sizeof(DevSpring) * nspr);
+    const size_t off_desc = off_drv + align256(sizeof(DevDrive) * ndrv);
+    if (off_desc + sizeof(BoxDesc) * (size_t)nsys > kNoAllocScratch) return LBM_E_ARG;
+    void *base = nullptr;
+    if (int rc = scratch_on_current_device(&base)) return rc;
+    char *p = (char *)base;
+    DevBody *g_bodies = (DevBody *)p;
+    DevSpring *g_springs = (DevSpring *)(p + off_spr);
+    DevDrive *g_drives = (DevDrive *)(p + off_drv);
+    BoxDesc *g_desc = (BoxDesc *)(p + off_desc);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = stage_records(g_bodies, bodies, nbod, [](const lbm_body &x) { return to_dev(x); }, st);
+    if (!rc) rc = stage_records(g_springs, springs, nspr, [](const lbm_spring &x) { return to_dev_spring(x); }, st);
+    if (!rc) rc = stage_records(g_drives, drives, ndrv, [](const lbm_drive &x) { return to_dev_drive(x); }, st);
+    if (!rc) {
+        struct Sys { int s; };
+        constexpr size_t kChunk = 16;
+        Sys idx[kChunk];
+        for (size_t s0 = 0; s0 < (size_t)nsys && !rc; s0 += kChunk) {
+            const size_t m = std::min(kChunk, (size_t)nsys - s0);
+            for (size_t q = 0; q < m; ++q) idx[q].s = (int)(s0 + q);
+            rc = stage_records(g_desc + s0, idx, m, [&](const Sys &x) {
+                return vacuum_desc(x.s, nb, ns, nd, g_bodies, g_springs, g_drives, traj, traj_cap);
+            }, st);
+        }
+    }
+    if (rc) return rc;
+    hipLaunchKernelGGL(vacuum_kernel, dim3(nsys), dim3(kCoupleThreads), 0, st, g_desc, (long long)nsteps);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return LBM_E_HIP;
+    // results through buffers on the stack
+    constexpr size_t kChunk = 16;
+    if (out) {
+        DevBody buf[kChunk];
+        for (size_t q0 = 0; q0 < nbod; q0 += kChunk) {
+            const size_t m = std::min(kChunk, nbod - q0);
+            if (hipMemcpyAsync(buf, g_bodies + q0, sizeof(DevBody) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return LBM_E_HIP;
+            for (size_t q = 0; q < m; ++q) out[q0 + q] = from_dev(buf[q]);
+        }
+    }
+    int status[kChunk];
+    for (size_t s0 = 0; s0 < (size_t)nsys; s0 += kChunk) {
+        const size_t m = std::min(kChunk, (size_t)nsys - s0);
+        for (size_t q = 0; q < m; ++q)
+            if (hipMemcpyAsync(&status[q], &g_desc[s0 + q].status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+                return LBM_E_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return LBM_E_HIP;
+        for (size_t q = 0; q < m; ++q)
+            if (status[q] == LBM_E_UNSTABLE) rc = LBM_E_UNSTABLE;
+    }
     return rc;
 }
 

@@ -278,11 +278,12 @@ class Sim(BatchSim):
         return J.value, np.array(list(g))
 
 
-def vacuum_run(cases, steps, traj_cap=0, device="cuda:0"):
+def vacuum_run(cases, steps, traj_cap=0, device="cuda:0", noalloc=False):
     """Integrator-only runs of the swimmers of ``cases`` (one system each, all
     with the same numbers of bodies, springs and drives) for ``steps`` steps
-    through ``lbm_vacuum_run``.  Returns (final body states per system, the
-    trajectory ring as numpy (systems, traj_cap, bodies, 16) or None)."""
+    through ``lbm_vacuum_run`` (``lbm_vacuum_run_noalloc`` with ``noalloc``).
+    Returns (final body states per system, the trajectory ring as numpy
+    (systems, traj_cap, bodies, 16) or None)."""
     lib = _abi.load()
     nb, ns, nd = len(cases[0].bodies), len(cases[0].springs), len(cases[0].drives)
     if any((len(c.bodies), len(c.springs), len(c.drives)) != (nb, ns, nd) for c in cases):
@@ -299,7 +300,7 @@ def vacuum_run(cases, steps, traj_cap=0, device="cuda:0"):
                        device=dev) if traj_cap else None
     with torch.cuda.device(dev):
         stream = torch.cuda.current_stream(dev).cuda_stream
-        run = lib.lbm_vacuum_run
+        run = lib.lbm_vacuum_run_noalloc if noalloc else lib.lbm_vacuum_run
         rc = run(bodies, nb, springs, ns, drives, nd, len(cases), int(steps),
                  C.c_void_p(traj.data_ptr()) if traj is not None else None, int(traj_cap), out, C.c_void_p(stream))
     if rc != _abi.LBM_OK:
