@@ -113,19 +113,46 @@ template <> struct Storage<bf16_t> {
     }
 };
 
-// Sums over the 64 lanes of a wave in a fixed xor-shuffle tree: every lane
-// gets the same total, and the order of the additions does not depend on
-// timing.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Sums over the 64 lanes of a wave in a fixed tree: every lane gets the
+// same total, and the order of the additions does not depend on timing.
+// The tree: lanes i and i^1, then i^2 (DPP quad permutations), the two
+// quads of each half row (row_half_mirror), the two halves of each row of 16
+// (row_mirror), and the four row sums as (r0 + r1) + (r2 + r3), read with
+// v_readlane.  DPP moves take a few cycles where a shuffle through the LDS
+// crossbar takes tens.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_move<CTRL>((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_move<CTRL>((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+__device__ __forceinline__ int read_lane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowHalfMirror = 0x141;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+    v += dpp_move<kDppQuadSwap1>(v);
+    v += dpp_move<kDppQuadSwap2>(v);
+    v += dpp_move<kDppRowHalfMirror>(v);
+    v += dpp_move<kDppRowMirror>(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_t(v); }
+__device__ __forceinline__ int wave_sum_int(int v) { return wave_sum_t(v); }
 
 // The owners of the 18 neighbours of a cell (0 fluid, 1 + b body b), five
 // bits each, six to a word: three registers, and no array that a run-time

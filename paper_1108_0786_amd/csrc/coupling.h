@@ -114,16 +114,23 @@ __device__ __forceinline__ double load_dev(const void *p, size_t i, float inv_sc
 // The records of body b are [rec_off[b], rec_off[b + 1]).  Wave w of the
 // workgroup adds those of bodies w, w + 4, ...: lane l takes records l,
 // l + 64, ... of the range in that order (four loads in flight), and the
-// lanes are added in a fixed xor-shuffle tree.  The sums go to sh.psum /
+// lanes are added in a fixed tree (wave_sum).  The sums go to sh.psum /
 // sh.psumi; the body table is not needed yet, so this runs while the tables
 // are being staged.
-// B is the kernel's snapshot of the descriptor and Bg the descriptor itself:
-// the offsets are read from Bg, as an index into the snapshot's array would
-// move the whole snapshot out of registers.
-__device__ __forceinline__ void sum_records(const BoxDesc &B, const BoxDesc &Bg, CoupleShared &sh) {
+// The offsets come from the kernel's snapshot of the descriptor, picked by
+// constant indices (an index computed at run time into the snapshot's array
+// would move the whole snapshot out of registers).
+__device__ __forceinline__ int rec_off_at(const BoxDesc &B, int b) {
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q <= kMaxBodies; ++q) v = b == q ? B.rec_off[q] : v;
+    return v;
+}
+
+__device__ __forceinline__ void sum_records(const BoxDesc &B, CoupleShared &sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int b = wave; b < B.nb; b += kCoupleThreads / 64) {
-        const int h0 = min(Bg.rec_off[b], B.link_cap), h1 = min(Bg.rec_off[b + 1], B.link_cap);
+        const int h0 = min(rec_off_at(B, b), B.link_cap), h1 = min(rec_off_at(B, b + 1), B.link_cap);
         double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int ia[6] = {0, 0, 0, 0, 0, 0};
         for (int h = h0 + lane; h < h1; h += 4 * 64) {
@@ -373,17 +380,21 @@ __device__ __forceinline__ void decide_map(const BoxDesc &B, BoxDesc &Bg, Couple
     const bool all_finite = !__any(!finite);
     const bool any_need = force || __any(need);
     const bool any_soon = __any(soon);
+    const int nmap = all_finite && any_need ? 1 : 0;
+    if (b == 0) {
+        if (!all_finite) Bg.status = -4;
+        sh.map_req = nmap;
+        sh.share_next = nmap || any_soon;
+    }
+    // the cell box only when a remap is due (the decision is the same in
+    // every lane): 36 shuffles of doubles are a large part of a step without one
+    if (!nmap) return;
     for (int m = 32; m >= 1; m >>= 1)
         for (int q = 0; q < 3; ++q) {
             lo[q] = fmin(lo[q], __shfl_xor(lo[q], m));
             hi[q] = fmax(hi[q], __shfl_xor(hi[q], m));
         }
     if (b != 0) return;
-    const int nmap = all_finite && any_need ? 1 : 0;
-    if (!all_finite) Bg.status = -4;
-    sh.map_req = nmap;
-    sh.share_next = nmap || any_soon;
-    if (!nmap) return;
     const int n[3] = {B.nx, B.ny, B.nz};
     for (int q = 0; q < 3; ++q) {
         // clamp in double before converting, so that no integer overflows
@@ -1009,7 +1020,8 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
                                                                 double *qmaps, double *margins,
                                                                 int mode, int force_map, int coop) {
     __shared__ CoupleShared sh;
-    const int bi = active[blockIdx.x / kRedBlocks];
+    // active == null: every box of the context takes part, in order
+    const int bi = active ? active[blockIdx.x / kRedBlocks] : (int)(blockIdx.x / kRedBlocks);
     const int r = blockIdx.x % kRedBlocks;
     BoxDesc &Bg = boxes[bi];
     // snapshot of the descriptor, taken before this kernel stores into it, so
@@ -1028,10 +1040,13 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     // One thread per workgroup counts and reads; the whole workgroup must
     // take the same decision.
     if (threadIdx.x == 0) {
+        // both hints are read while the count is in flight
+        const int h0 = __hip_atomic_load(&ctl->share[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int h1 = __hip_atomic_load(&ctl->share[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrival =
             __hip_atomic_fetch_add(&ctl->launches, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sh.parity = (int)((arrival / kRedBlocks) & 1u);
-        sh.hint = __hip_atomic_load(&ctl->share[sh.parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.hint = sh.parity ? h1 : h0;
     }
     __syncthreads();
     const int parity = sh.parity;
@@ -1047,7 +1062,7 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         }
         Staged st;
         stage_load(B, sh, qm, mg, st);
-        if (mode == kModeStep) sum_records(B, Bg, sh);
+        if (mode == kModeStep) sum_records(B, sh);
         stage_store(B, sh, qm, mg, st);
         if (mode == kModeStep) {
             finish_forces(B, sh);

@@ -411,6 +411,8 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
 // Coupling kernel: kRedBlocks workgroups per active box.
 int launch_couple(lbm_ctx *c, const int *active_dev, int nactive, int mode) {
     if (nactive == 0) return LBM_OK;
+    // every box active (the list is built in box order): no list to read
+    if (active_dev == c->d_active && nactive == (int)c->boxes.size()) active_dev = nullptr;
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         // cooperative only if every workgroup of the launch is resident at once

@@ -109,7 +109,7 @@ struct PushAll<S, 19> {
 // links are numbered in cell order, so the wave's links are one contiguous
 // range [l0, l1): lane q takes links l0 + q, l0 + q + 64, ... (coalesced
 // loads of the scratch records, a pass or two), the wave adds the lanes in
-// a fixed xor-shuffle tree, and lane 0 writes the sums to the record that
+// a fixed tree (wave_sum), and lane 0 writes the sums to the record that
 // the mapping reserved for (this wave, body b): record grp_pos[l0 + n] for
 // the wave's n-th body in ascending order.  The sums come out the same bit
 // for bit however the sweep is launched.  The populations are no longer
