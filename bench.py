@@ -344,6 +344,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-periods", type=int, default=10)
+    ap.add_argument("--streaming", choices=("default", "0", "1"), default="default",
+                    help="population streaming of every leg: the library's default per storage, "
+                         "0 two buffers, 1 in place")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the reverse pass on the 128x64x64 adjoint workload")
     ap.add_argument("--cpu-configs", action="store_true",
@@ -360,8 +363,9 @@ def main():
     if "f32" not in legs:
         legs = ["f32"] + legs
     results = {}
+    tune = None if args.streaming == "default" else {"streaming": int(args.streaming)}
     for st in legs:
-        results[st] = time_leg(W.plain_at_scale(storage=st), st, args.steps, args.warmup)
+        results[st] = time_leg(W.plain_at_scale(storage=st), st, args.steps, args.warmup, tune=tune)
     head = results["f32"]
     case = W.plain_at_scale(storage="f32")
     copy_gbs = copy_ceiling()
@@ -393,7 +397,8 @@ def main():
                    "cells": case.ncells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(head["sweep_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "sweep_aa_kernel<float> (in-place streaming, mean of even and odd steps)",
+                     "kernel": ("sweep_kernel<float> (two buffers)" if args.streaming == "0" else
+                                "sweep_aa_kernel<float> (in-place streaming, mean of even and odd steps)"),
                      "bytes_per_launch": head["sweep_bytes"],
                      "launch_us": round(head["sweep_us"], 2), "copy_ceiling_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(head["sweep_gbs"] / copy_gbs, 4),

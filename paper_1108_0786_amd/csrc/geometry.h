@@ -18,14 +18,15 @@ __device__ __forceinline__ int wrap_centered(int d, int L) {
 
 // r = (d + 1/2) - f, with R = floor(X), f = X - R, d = cell - R (wrapped on
 // periodic axes); also returns the integer offsets d.
-__device__ __forceinline__ void lever_arm(const DevBody &b, int i, int j, int k, int nx, int ny,
-                                          int nz, int per, double r[3], int d[3]) {
+// X: the body position, anchor + D, per axis.
+__device__ __forceinline__ void lever_arm_at(const double X3[3], int i, int j, int k, int nx, int ny, int nz,
+                                             int per, double r[3], int d[3]) {
 #pragma clang fp contract(off)
     const int idx[3] = {i, j, k};
     const int n[3] = {nx, ny, nz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double X = b.anchor[a] + b.D[a];
+        double X = X3[a];
         double R = floor(X);
         double f = X - R;
         // R is converted through a clamp so that a non-finite or huge position
@@ -35,6 +36,13 @@ __device__ __forceinline__ void lever_arm(const DevBody &b, int i, int j, int k,
         d[a] = di;
         r[a] = ((double)di + 0.5) - f;
     }
+}
+
+__device__ __forceinline__ void lever_arm(const DevBody &b, int i, int j, int k, int nx, int ny,
+                                          int nz, int per, double r[3], int d[3]) {
+#pragma clang fp contract(off)
+    const double X[3] = {b.anchor[0] + b.D[0], b.anchor[1] + b.D[1], b.anchor[2] + b.D[2]};
+    lever_arm_at(X, i, j, k, nx, ny, nz, per, r, d);
 }
 
 __device__ __forceinline__ void body_axis(const DevBody &b, double a[3]) {
