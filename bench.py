@@ -35,13 +35,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 
-# HBM bytes per FP32 sweep launch at 256x128x128, from two rocprofv3 counter
-# passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors make the counters
-# read 2 GiB for a 2 GiB copy).  Valid only for the kernel sources whose
-# digest is given; a changed kernel reports null until it is measured again.
-SWEEP_TRAFFIC = {"bytes": 647190592,
+# HBM bytes per launch of the default FP32 sweep (in place) at 256x128x128,
+# the mean of even and odd steps, from two rocprofv3 counter passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0; the factors make the counters read
+# 2 GiB for a 2 GiB copy).  Valid only for the kernel sources whose digest is
+# given; a changed kernel reports null until it is measured again.
+SWEEP_TRAFFIC = {"bytes": 659923967,
                  "sources": ("common.h", "geometry.h", "sweep.h", "sweep_aa.h"),
-                 "sha256": "2d3d75ec8bb242179dd3ccb0fd255f664cf64dbf8541935300ac8b6a8c4acf61"}
+                 "sha256": "0adfb4ee5cb9267ad413b8a051dc76334a310ee66cf81cd1fa2e9a6224c0a35e"}
 
 
 def measured_traffic():
@@ -396,7 +397,8 @@ def main():
                                "r 6, rest length 24, FP32 shifted populations",
                    "cells": case.ncells, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(head["sweep_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "unit": "GB/s", "frac": round(head["sweep_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if args.streaming == "default" else None,
                      "kernel": ("sweep_kernel<float> (two buffers)" if args.streaming == "0" else
                                 "sweep_aa_kernel<float> (in-place streaming, mean of even and odd steps)"),
                      "bytes_per_launch": head["sweep_bytes"],

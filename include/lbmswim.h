@@ -78,7 +78,12 @@ enum {
 };
 
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
-enum { LBM_SPHERE = 0, LBM_CAPSULE = 1 };
+/* LBM_SLAB is for tests only: the half-space r . axis > 0 beyond the plane
+ * through the body position normal to the body's x axis (a moving wall for
+ * Couette flow, Sec. 2.3).  It must be kinematic (kinematic = 1), may reach
+ * the walls, and must not overlap other bodies; radius, half_len, mass and
+ * inertia are not used. */
+enum { LBM_SPHERE = 0, LBM_CAPSULE = 1, LBM_SLAB = 2 };
 
 /* doubles per body per step in the trajectory record:
  * disp[3], vel[3], omega[3], F_hydro[3], T_hydro[3], step */
@@ -113,6 +118,15 @@ typedef struct {
                                  coupling amplifies for tau < 1.  lbm_adjoint
                                  differentiates either form. */
     int32_t reserved;         /* must be 0 */
+    double body_force[3];     /* TEST ONLY, not part of the method: a uniform
+                                 force per unit volume on the fluid (lattice
+                                 units), entered by Guo's scheme (velocity
+                                 u = (j + g/2)/rho in the equilibrium, source
+                                 (1 - 1/(2 tau)) w [3 (e - u) + 9 (e.u) e].g),
+                                 for Poiseuille flow and the drag of a sphere
+                                 array.  Zero for every workload of the paper.
+                                 A box with a force cannot sample a flow
+                                 average or run lbm_adjoint (LBM_E_STATE). */
 } lbm_params;
 
 /* A rigid body (Sec. 2.2).  Positions are anchor + disp; disp accumulates
@@ -123,7 +137,7 @@ typedef struct {
  * kinematic = 2: its rotation is locked (omega prescribed, torque still
  * computed) while it translates freely; 0: free. */
 typedef struct {
-    int32_t shape;            /* LBM_SPHERE or LBM_CAPSULE */
+    int32_t shape;            /* LBM_SPHERE, LBM_CAPSULE, or LBM_SLAB (tests) */
     int32_t kinematic;        /* 0 free, 1 prescribed motion, 2 rotation locked */
     double radius, half_len;  /* half_len: half the cylinder length of a capsule */
     double mass, inertia[3];
@@ -346,10 +360,10 @@ int lbm_vacuum_run(const lbm_body *bodies, int32_t nb, const lbm_spring *springs
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments, run and results, with no hipMalloc or hipFree.  The
  * device tables of the nsys systems (bodies, springs, drives and one
- * descriptor per system: 256 nb + 32 ns + 56 nd + 320 bytes per system, each
+ * descriptor per system: 256 nb + 32 ns + 56 nd + 344 bytes per system, each
  * of the four tables padded to 256 bytes) go into an array of
  * LBM_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
- * on until the process ends (860 systems of three beads, two springs and one
+ * on until the process ends (850 systems of three beads, two springs and one
  * drive fit); the caller still owns traj and out.  LBM_E_ARG when the
  * tables do not fit, or for the argument errors of lbm_vacuum_run.  Every
  * call on one GPU uses that GPU's array, so calls that overlap in time on

@@ -31,7 +31,8 @@ class LbmParams(C.Structure):
                 ("storage", C.c_int32), ("shift_log2", C.c_int32),
                 ("pop", C.c_void_p * 2), ("flags", C.c_void_p),
                 ("traj", C.c_void_p), ("traj_cap", C.c_int64), ("stream", C.c_void_p),
-                ("stride", C.c_int64), ("force_average", C.c_int32), ("reserved", C.c_int32)]
+                ("stride", C.c_int64), ("force_average", C.c_int32), ("reserved", C.c_int32),
+                ("body_force", C.c_double * 3)]
 
 
 class LbmBody(C.Structure):

@@ -28,6 +28,7 @@ __host__ __device__ constexpr int two_w36(int a) { return a == 0 ? 24 : (a <= 6 
 
 constexpr int kBodyShapeSphere = 0;
 constexpr int kBodyShapeCapsule = 1;
+constexpr int kBodyShapeSlab = 2;     // tests only: a half-space
 constexpr uint8_t kNearBit = 0x80;
 constexpr uint8_t kOwnerMask = 0x7f;
 
@@ -259,6 +260,7 @@ struct BoxDesc {
     int *flow_count;           // N: samples in which the cell was fluid
     int flow_every;            // sample the steps n with n % flow_every == 0 (0: none)
     int aa;                    // 1: the populations stream in place in pop0 or pop1 (layout by step parity)
+    double force[3];           // tests only: uniform body force on the fluid (Guo's scheme)
     // mutable state, advanced on the device
     long long step;
     int cur;                   // index of the buffer holding the current populations

@@ -321,6 +321,7 @@ __device__ __forceinline__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, Couple
 // 3. object mapping
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double body_extent(const DevBody &b) {
+    if (b.shape == kBodyShapeSlab) return 1e30;   // a half-space: the whole box
     return b.radius + (b.shape == kBodyShapeCapsule ? b.half_len : 0.0);
 }
 
@@ -333,7 +334,7 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
         dx += t * t;
     }
     double bound = sqrt(dx);
-    if (b.shape == kBodyShapeCapsule) {
+    if (b.shape != kBodyShapeSphere) {
         // rotation angle between q and qmap: 2 atan2(|v|, |w|) of q * conj(qmap)
         const double *p = b.q;
         const double w = p[0] * qmap[0] + p[1] * qmap[1] + p[2] * qmap[2] + p[3] * qmap[3];
@@ -341,7 +342,9 @@ __device__ __forceinline__ double moved_bound(const DevBody &b, const double qma
         const double vy = -p[0] * qmap[2] + p[2] * qmap[0] - p[3] * qmap[1] + p[1] * qmap[3];
         const double vz = -p[0] * qmap[3] + p[3] * qmap[0] - p[1] * qmap[2] + p[2] * qmap[1];
         const double ang = 2.0 * atan2(sqrt(vx * vx + vy * vy + vz * vz), fabs(w));
-        bound += ang * (b.half_len + b.radius + 2.0);
+        // a turned half-space moves without bound far from its centre
+        if (b.shape == kBodyShapeSlab) bound = ang > 0.0 ? 1e300 : bound;
+        else bound += ang * (b.half_len + b.radius + 2.0);
     }
     return bound;
 }
@@ -366,9 +369,9 @@ __device__ __forceinline__ void decide_map(const BoxDesc &B, BoxDesc &Bg, Couple
         // speeds (only decides whether the next step's workgroups stay to
         // share the work; see couple_kernel)
         double ahead = moved + 2.0 * sqrt(bd.V[0] * bd.V[0] + bd.V[1] * bd.V[1] + bd.V[2] * bd.V[2]) + 1e-6;
-        if (bd.shape == kBodyShapeCapsule)
-            ahead += 2.0 * sqrt(bd.O[0] * bd.O[0] + bd.O[1] * bd.O[1] + bd.O[2] * bd.O[2]) *
-                     (bd.half_len + bd.radius + 2.0);
+        const double spin = sqrt(bd.O[0] * bd.O[0] + bd.O[1] * bd.O[1] + bd.O[2] * bd.O[2]);
+        if (bd.shape == kBodyShapeCapsule) ahead += 2.0 * spin * (bd.half_len + bd.radius + 2.0);
+        if (bd.shape == kBodyShapeSlab && spin > 0.0) ahead = 1e300;
         soon = !(ahead < sh.margin[b] - kMarginSafety);
         const double ext = body_extent(bd);
         for (int q = 0; q < 3; ++q) {
@@ -478,7 +481,7 @@ __device__ __forceinline__ double map_margin(const BoxDesc &B, const DevBody &bd
         double r[3];
         int d[3];
         lever_arm(bd, i, j, k, B.nx, B.ny, B.nz, B.per, r, d);
-        mm = fmin(mm, fabs(sqrt(core_dist2(bd, r)) - bd.radius));
+        mm = fmin(mm, surface_dist(bd, r));
     }
     return mm;
 }

@@ -68,9 +68,24 @@ __device__ __forceinline__ double core_dist2(const DevBody &b, const double r[3]
     return (sx * sx + sy * sy) + sz * sz;
 }
 
+// Signed distance along the body's x axis (the slab's normal).
+__device__ __forceinline__ double axial(const DevBody &b, const double r[3]) {
+#pragma clang fp contract(off)
+    double a[3];
+    body_axis(b, a);
+    return (r[0] * a[0] + r[1] * a[1]) + r[2] * a[2];
+}
+
 __device__ __forceinline__ bool inside(const DevBody &b, const double r[3]) {
 #pragma clang fp contract(off)
+    if (b.shape == kBodyShapeSlab) return axial(b, r) > 0.0;
     return core_dist2(b, r) <= b.radius * b.radius;
+}
+
+// Distance of a point from the body's surface (the margin of the remap skip).
+__device__ __forceinline__ double surface_dist(const DevBody &b, const double r[3]) {
+    if (b.shape == kBodyShapeSlab) return fabs(axial(b, r));
+    return fabs(sqrt(core_dist2(b, r)) - b.radius);
 }
 
 // u_w = V + Omega x r

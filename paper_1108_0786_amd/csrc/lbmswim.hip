@@ -71,6 +71,7 @@ struct lbm_ctx {
     bool coop_remap = true;        // share the mapping among a box's coupling workgroups
     bool aa = false;               // stream in place (one buffer, layout by step parity)
     bool flow_any = false;         // some box samples the time-averaged flow
+    bool force_any = false;        // some box has the test-only body force
     int coop_blocks = 0;           // coupling workgroups that are surely resident at once
     bool poisoned = false;
     bool timing = false;
@@ -145,6 +146,8 @@ int validate_params(lbm_ctx *c, const lbm_params &p) {
         return fail(c, LBM_E_ARG, "shift_log2 out of range");
     if (p.force_average != 0 && p.force_average != 1) return fail(c, LBM_E_ARG, "force_average must be 0 or 1");
     if (p.reserved != 0) return fail(c, LBM_E_ARG, "reserved must be 0");
+    for (int q = 0; q < 3; ++q)
+        if (!std::isfinite(p.body_force[q])) return fail(c, LBM_E_ARG, "body force not finite");
     return LBM_OK;
 }
 
@@ -188,6 +191,7 @@ BoxDesc make_desc(const HostBox &h, int storage, bool aa) {
     d.flow_count = h.flow_count;
     d.flow_every = h.flow_every;
     d.aa = aa ? 1 : 0;
+    for (int q = 0; q < 3; ++q) d.force[q] = h.p.body_force[q];
     return d;
 }
 
@@ -216,6 +220,8 @@ int init_common(const lbm_params *params, int nbox, lbm_ctx **out) {
     if (!params || nbox < 1 || nbox > 65535) return LBM_E_ARG;
     lbm_ctx *c = new lbm_ctx();
     c->storage = params[0].storage;
+    for (int b = 0; b < nbox; ++b)
+        for (int q = 0; q < 3; ++q) c->force_any = c->force_any || params[b].body_force[q] != 0.0;
     c->stream = (hipStream_t)params[0].stream;
     for (int b = 0; b < nbox; ++b) {
         int rc = validate_params(c, params[b]);
@@ -355,7 +361,18 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
     const int n[3] = {h.p.nx, h.p.ny, h.p.nz};
     for (int b = 0; b < nb; ++b) {
         const lbm_body &B = bodies[b];
-        if (B.shape != LBM_SPHERE && B.shape != LBM_CAPSULE) return fail(c, LBM_E_ARG, "unknown body shape");
+        if (B.shape != LBM_SPHERE && B.shape != LBM_CAPSULE && B.shape != LBM_SLAB)
+            return fail(c, LBM_E_ARG, "unknown body shape");
+        if (B.shape == LBM_SLAB) {
+            // tests only: a kinematic half-space; it reaches the walls by design
+            if (B.kinematic != 1) return fail(c, LBM_E_ARG, "a slab must be kinematic");
+            const double qn = std::sqrt(B.quat[0] * B.quat[0] + B.quat[1] * B.quat[1] + B.quat[2] * B.quat[2] +
+                                        B.quat[3] * B.quat[3]);
+            if (std::fabs(qn - 1.0) > 1e-6) return fail(c, LBM_E_ARG, "quaternion must be normalised");
+            for (int q = 0; q < 3; ++q)
+                if (!std::isfinite(B.anchor[q] + B.disp[q])) return fail(c, LBM_E_ARG, "body position not finite");
+            continue;
+        }
         if (B.kinematic < 0 || B.kinematic > 2) return fail(c, LBM_E_ARG, "kinematic must be 0, 1 or 2");
         if (!(B.radius > 0) || B.half_len < 0 || (B.kinematic != 1 && !(B.mass > 0)))
             return fail(c, LBM_E_ARG, "body radius and mass must be positive");
@@ -379,6 +396,7 @@ int validate_bodies(lbm_ctx *c, const HostBox &h, const lbm_body *bodies, int nb
         }
         for (int o = 0; o < b; ++o) {
             const lbm_body &O = bodies[o];
+            if (O.shape == LBM_SLAB) continue;   // not checked against a slab (tests only)
             // core segments, the other body moved to its nearest periodic image
             double ao[3], p0[3], d0[3], p1[3], d1[3];
             core_half_axis(O, ao);
@@ -495,8 +513,21 @@ int launch_sweep_f(lbm_ctx *c) {
 
 // The sweep that also samples the time-averaged flow runs only while some
 // box samples it; the plain sweep carries no trace of it.
+// The sweep with the test-only body force (plain loads, no flow sampling).
+template <typename S, int BLOCK>
+int launch_sweep_forced(lbm_ctx *c) {
+    if (c->aa)
+        hipLaunchKernelGGL((sweep_aa_kernel<S, BLOCK, false, false, true>), dim3(c->ngrid), dim3(BLOCK), 0,
+                           c->stream, c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+    else
+        hipLaunchKernelGGL((sweep_kernel<S, BLOCK, false, false, true>), dim3(c->ngrid), dim3(BLOCK), 0, c->stream,
+                           c->d_boxes, c->d_work, c->nwork, c->xcd_order);
+    return LBM_OK;
+}
+
 template <typename S, int BLOCK>
 int launch_sweep_t(lbm_ctx *c) {
+    if (c->force_any) return launch_sweep_forced<S, BLOCK>(c);
     return c->flow_any ? launch_sweep_f<S, BLOCK, true>(c) : launch_sweep_f<S, BLOCK, false>(c);
 }
 
@@ -1068,6 +1099,7 @@ int lbm_adjoint(lbm_ctx *c, int64_t nsteps, int32_t checkpoint_every, const doub
     if (c->boxes[0].limit >= 0) return fail(c, LBM_E_ARG, "the adjoint box must not have a step limit");
     if (c->boxes[0].bodies.empty()) return fail(c, LBM_E_STATE, "no bodies set");
     if (c->flow_any) return fail(c, LBM_E_STATE, "stop the flow average before the adjoint (its recomputation would sample)");
+    if (c->force_any) return fail(c, LBM_E_STATE, "the adjoint does not cover the test-only body force");
     // the reverse pass keeps and replays its states in the two-buffer layout
     const bool was_aa = c->aa;
     if (was_aa && (rc = set_streaming(c, false))) return rc;
@@ -1251,6 +1283,12 @@ int lbm_set_bodies_box(lbm_ctx *c, int32_t box, const lbm_body *bodies, int32_t 
     // link capacity: 18 links per cell of every body's bounding box plus one layer
     long long cap = 0;
     for (const auto &b : h.bodies) {
+        if (b.shape == LBM_SLAB) {
+            // a plane across the box: at most every face cell of the box twice over
+            const long long nx = h.p.nx, ny = h.p.ny, nz = h.p.nz;
+            cap += 18 * 2 * (nx * ny + ny * nz + nz * nx);
+            continue;
+        }
         const double e = body_extent_h(b) + 2.5;
         const long long side = (long long)std::ceil(2 * e) + 1;
         cap += 18 * side * side * side;
@@ -1495,6 +1533,7 @@ int lbm_flow_average_begin(lbm_ctx *c, int32_t box, int32_t every) {
     int rc = check_box(c, box);
     if (rc) return rc;
     if (every < 0) return fail(c, LBM_E_ARG, "every must be >= 0");
+    if (every > 0 && c->force_any) return fail(c, LBM_E_STATE, "no flow average with the test-only body force");
     HostBox &h = c->boxes[box];
     if (every > 0) {
         if (!h.flow_sum) {

@@ -253,6 +253,53 @@ __device__ __forceinline__ C collide(C *f, C omega) {
     return rho;
 }
 
+// The collision with the test-only uniform body force g (Guo's scheme; not
+// part of the method): the equilibrium takes u = (j + g/2) / rho, and each
+// direction gains (1 - 1/(2 tau)) w [3 (e - u) + 9 (e.u) e].g.  Used only
+// by boxes that set a force (Poiseuille flow, the drag of a sphere array).
+template <typename C>
+__device__ __forceinline__ C collide_forced(C *f, C omega, const double *gd) {
+#pragma clang fp contract(off)
+    const C g[3] = {(C)gd[0], (C)gd[1], (C)gd[2]};
+    C drho = f[0];
+#pragma unroll
+    for (int a = 1; a < 19; ++a) drho += f[a];
+    C jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
+    C jy = (f[3] - f[4]) + (f[7] - f[8]) + (f[10] - f[9]) + (f[15] - f[16]) + (f[17] - f[18]);
+    C jz = (f[5] - f[6]) + (f[11] - f[12]) + (f[14] - f[13]) + (f[15] - f[16]) + (f[18] - f[17]);
+    jx = jx + C(0.5) * g[0];
+    jy = jy + C(0.5) * g[1];
+    jz = jz + C(0.5) * g[2];
+    const C rho = C(1) + drho;
+    const C inv = C(1) / rho;
+    const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
+    const C usq15 = C(1.5) * fmac(ux, ux, fmac(uy, uy, uz * uz));
+    const C pref = C(1) - C(0.5) * omega;
+    // sources first, from the pre-collision u
+    C src[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+        const C eu = (C)ex(a) * ux + (C)ey(a) * uy + (C)ez(a) * uz;
+        const C s = (C(3) * ((C)ex(a) - ux) + C(9) * eu * (C)ex(a)) * g[0] +
+                    (C(3) * ((C)ey(a) - uy) + C(9) * eu * (C)ey(a)) * g[1] +
+                    (C(3) * ((C)ez(a) - uz) + C(9) * eu * (C)ez(a)) * g[2];
+        src[a] = pref * C(wgt(a)) * s;
+    }
+    f[0] = fmac(omega, C(wgt(0)) * (drho - rho * usq15) - f[0], f[0]);
+    relax_pair<C, 1>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 3>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 5>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 7>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 9>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 11>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 13>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 15>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+    relax_pair<C, 17>(f, drho, rho, ux, uy, uz, jx, jy, jz, usq15, omega);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) f[a] = f[a] + src[a];
+    return rho;
+}
+
 // Time-averaged flow field (the averaged flow fields of Sec. 6): add the
 // fluid velocity u = j / rho of this cell's pre-collision state to the box's
 // sums, in double, with the moments summed over the directions in ascending
@@ -359,7 +406,7 @@ __device__ __forceinline__ int tile_index(int xcd_order) {
 // 5 for double, one fewer while sampling the flow average: without the hint
 // the register allocator settles one register above 72 for the float
 // sweep, which costs a wave per SIMD.
-template <typename S, int BLOCK, bool NT, bool FLOW>
+template <typename S, int BLOCK, bool NT, bool FLOW, bool FORCE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 5 : (FLOW ? 6 : 7), 8)))
 void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
                                                       int xcd_order) {
@@ -401,7 +448,9 @@ void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
         if (valid && fluid && B.flow_every > 0 && B.step % B.flow_every == 0) flow_sample<C>(B, cell, f);
     }
     const C omega = sizeof(C) == 8 ? (C)B.omega : (C)B.omegaf;
-    const C rho = collide<C>(f, omega);
+    C rho;
+    if constexpr (FORCE) rho = collide_forced<C>(f, omega, B.force);
+    else rho = collide<C>(f, omega);
     const int nx = B.nx, ny = B.ny, nz = B.nz, per = B.per;
     const int sy = nx, sz = nx * ny;
     const bool at_lo[3] = {i == 0, j == 0, k == 0};

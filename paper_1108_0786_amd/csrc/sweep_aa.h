@@ -144,7 +144,7 @@ struct KeepFast<S, NT, 19> {
 // (B.step), so the boxes of a batch may be at different parities, and a
 // replayed graph needs no parity of its own.  Both parities share one
 // kernel: the branch is uniform over the workgroup.
-template <typename S, int BLOCK, bool NT, bool FLOW>
+template <typename S, int BLOCK, bool NT, bool FLOW, bool FORCE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 5 : (FLOW ? 6 : 7), 8)))
 void sweep_aa_kernel(BoxDesc *boxes, const WorkItem *work, int nwork, int xcd_order) {
     using St = Storage<S>;
@@ -212,7 +212,7 @@ void sweep_aa_kernel(BoxDesc *boxes, const WorkItem *work, int nwork, int xcd_or
         if (fluid && B.flow_every > 0 && B.step % B.flow_every == 0) flow_sample<C>(B, cell, f);
     }
     const C omega = sizeof(C) == 8 ? (C)B.omega : (C)B.omegaf;
-    const C rho = collide<C>(f, omega);
+    const C rho = FORCE ? collide_forced<C>(f, omega, B.force) : collide<C>(f, omega);
     if (!odd) {
         if (near) {
             St::store(pop, (size_t)cell, f[0], B.scale);

@@ -69,7 +69,7 @@ DEFAULT_PAD = 1024
 class _Box:
     """Device buffers of one box (caller-owned memory of the C-ABI)."""
 
-    def __init__(self, case, storage, device, traj_cap, shift_log2, pad=None):
+    def __init__(self, case, storage, device, traj_cap, shift_log2, pad=None, body_force=None):
         self.case = case
         self.N = case.nx * case.ny * case.nz
         self.stride = padded_stride(self.N, pad)
@@ -93,6 +93,9 @@ class _Box:
         p.stream = torch.cuda.current_stream(device).cuda_stream
         p.stride = self.stride
         p.force_average = int(bool(getattr(case, "force_average", False)))
+        if body_force is not None:            # test-only uniform force on the fluid
+            for q in range(3):
+                p.body_force[q] = float(body_force[q])
         self.params = p
 
 
@@ -100,7 +103,7 @@ class BatchSim:
     """Many independent boxes, each with its own swimmer, in one context."""
 
     def __init__(self, cases, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None,
-                 pad=None, tune=None):
+                 pad=None, tune=None, body_force=None):
         self.lib = _abi.load()
         self.device = torch.device(device)
         storage = storage or cases[0].storage
@@ -108,7 +111,7 @@ class BatchSim:
         if shift_log2 is None:
             shift_log2 = cases[0].shift_log2 if storage in ("f16s", "bf16s") else 0
         with torch.cuda.device(self.device):
-            self.boxes = [_Box(c, storage, self.device, traj_cap, shift_log2, pad) for c in cases]
+            self.boxes = [_Box(c, storage, self.device, traj_cap, shift_log2, pad, body_force) for c in cases]
             arr = (LbmParams * len(cases))(*[b.params for b in self.boxes])
             self.ctx = C.c_void_p()
             rc = self.lib.lbm_init_batch(arr, len(cases), C.byref(self.ctx))
@@ -252,9 +255,10 @@ class Sim(BatchSim):
     """One box: ``Sim(case)`` maps ``case.bodies`` and is ready to step."""
 
     def __init__(self, case, storage=None, device="cuda:0", traj_cap=0, shift_log2=None, df0=None,
-                 pad=None, tune=None):
+                 pad=None, tune=None, body_force=None):
         super().__init__([case], storage=storage, device=device, traj_cap=traj_cap,
-                         shift_log2=shift_log2, df0=None if df0 is None else [df0], pad=pad, tune=tune)
+                         shift_log2=shift_log2, df0=None if df0 is None else [df0], pad=pad, tune=tune,
+                         body_force=body_force)
 
     def centroid_displacement(self):
         b = self.bodies()

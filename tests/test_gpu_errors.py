@@ -43,6 +43,7 @@ def _init_rc(case, **changes):
     dict(tau=0.5), dict(tau=float("nan")), dict(nx=2), dict(storage=7), dict(periodic_mask=8),
     dict(flags=None), dict(reserved=1), dict(force_average=2), dict(stride=100),
     dict(traj=1, traj_cap=0),                   # a trajectory pointer without a capacity (never dereferenced)
+    dict(body_force=(C.c_double * 3)(float("nan"), 0.0, 0.0)),
 ])
 def test_invalid_parameters_are_rejected(changes):
     abi, _ = _lib()
