@@ -260,7 +260,10 @@ int lbm_step_count(lbm_ctx *ctx, int32_t box, int64_t *steps);
  * force or state became non-finite, LBM_E_CAPACITY if a link list overflowed,
  * LBM_E_SYNC if the workgroups of a cooperative mapping (LBM_TUNE_COOP_REMAP)
  * waited at a barrier for longer than about a second (they then give up, so
- * that the kernel always ends; the box's state is not valid afterwards). */
+ * that the kernel always ends; the box's state is not valid afterwards).
+ * Such a mapping only starts once all of the box's workgroups are running;
+ * if they are not within tens of microseconds (other work holds the device),
+ * the box's first workgroup maps alone instead, with the same results. */
 int lbm_status(lbm_ctx *ctx);
 
 /* Hand-written reverse mode (adjoint) of nsteps coupled steps of box 0 of a
@@ -302,8 +305,11 @@ int lbm_adjoint(lbm_ctx *ctx, int64_t nsteps, int32_t checkpoint_every, const do
  *   LBM_TUNE_COOP_REMAP   1 (default): when every workgroup of the coupling
  *                         launch can be resident at once (up to the device's
  *                         occupancy for it: a few boxes per launch), all
- *                         workgroups of a box share its mapping; 0: one
- *                         workgroup maps each box.  Results are identical.
+ *                         workgroups of a box share its mapping, once all of
+ *                         them have joined (else the first maps alone); 0:
+ *                         one workgroup maps each box; 2 (a test aid): the
+ *                         workgroups join as for 1, and the first one always
+ *                         maps alone.  Results are identical.
  *   LBM_TUNE_STREAMING    0: the sweep reads one population buffer and
  *                         pushes into the other (Eq. streaming as written;
  *                         default for LBM_F64, LBM_F16S, LBM_BF16S); 1

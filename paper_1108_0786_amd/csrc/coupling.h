@@ -27,6 +27,8 @@ constexpr int kMaxSprings = 64;
 constexpr int kMaxDrives = 16;
 constexpr double kMarginSafety = 1e-9;
 constexpr int kSpinLimit = 1 << 20;   // polls of a workgroup barrier before it gives up (about a second)
+constexpr int kJoinLimit = 64;        // polls the first workgroup waits for the others to join (tens of us)
+constexpr unsigned kJoinGo = 1u << 30, kJoinAbort = 1u << 31;
 
 enum : int { kModeStep = 0, kModeMapOnly = 1 };
 
@@ -44,6 +46,8 @@ struct CoupleCtl {
     unsigned owner_changes;      // cells whose owner a mapping has changed, counted since set-up
     int swapped;                 // published by the first workgroup: the remap sees the swapped layout
     unsigned reloc_count;        // stores listed by a remap in the swapped layout
+    unsigned join[2];            // by launch parity: workgroups that joined a shared remap, and the
+                                 // first workgroup's answer (kJoinGo / kJoinAbort)
 };
 
 struct CoupleShared {
@@ -889,6 +893,79 @@ __device__ __forceinline__ bool box_barrier(CoupleCtl *ctl, CoupleShared &sh, Bo
     return sh.sync_ok != 0;
 }
 
+// Joining a shared remap.  The box's other workgroups join this launch's
+// join word; the first workgroup, once it has published its decision, answers
+// kJoinGo when all of them have joined (they are then all resident, and the
+// remap's barriers can rely on it), or kJoinAbort when it maps alone: when
+// there is nothing to map (solo), or when they have not all joined within
+// kJoinLimit polls because some are not resident (other work on the device,
+// a launch larger than the device holds).  After kJoinAbort every other
+// workgroup, joined or not, leaves, and the first one maps by itself, with
+// the same results.  A joined workgroup that has waited kSpinLimit polls for
+// the answer withdraws, unless the answer came meanwhile.  Workgroups are
+// dispatched in order, so the first workgroup of a box is running whenever
+// one of the others is.  Returns true if this workgroup takes part in a
+// shared remap.
+__device__ __forceinline__ bool join_remap(CoupleCtl *ctl, CoupleShared &sh, int parity, bool lead, bool solo) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the decision, visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *J = &ctl->join[parity];
+        int go = 0;
+        if (lead) {
+            for (int spins = 0;;) {
+                const unsigned j = __hip_atomic_load(J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const bool all = (j & 0xffffu) == (unsigned)(kRedBlocks - 1);
+                if (!solo && !all && spins < kJoinLimit) {
+                    ++spins;
+                    __builtin_amdgcn_s_sleep(4);
+                    continue;
+                }
+                const unsigned answer = !solo && all ? kJoinGo : kJoinAbort;
+                unsigned e = j;
+                if (__hip_atomic_compare_exchange_strong(J, &e, j | answer, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    go = answer == kJoinGo;
+                    break;
+                }
+            }
+        } else {
+            bool joined = false;
+            for (;;) {
+                const unsigned j = __hip_atomic_load(J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (j & kJoinAbort) break;                          // too late: the first maps alone
+                unsigned e = j;
+                if (__hip_atomic_compare_exchange_strong(J, &e, j + 1u, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    joined = true;
+                    break;
+                }
+            }
+            for (int spins = 0; joined;) {
+                const unsigned j = __hip_atomic_load(J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (j & kJoinGo) {
+                    go = 1;
+                    break;
+                }
+                if (j & kJoinAbort) break;
+                if (spins >= kSpinLimit) {
+                    unsigned e = j;                                 // withdraw
+                    if (__hip_atomic_compare_exchange_strong(J, &e, j - 1u, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                    continue;
+                }
+                ++spins;
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sh.sync_ok = go;
+    }
+    __syncthreads();
+    return sh.sync_ok != 0;
+}
+
 // The whole mapping by the kRedBlocks workgroups of a box, r being this
 // one's rank: one contiguous slice of the cell range each, with a barrier
 // where a pass needs its neighbours' results.  The link count of every
@@ -1075,8 +1152,11 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     if (lead) {
         if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
         stage_out(B, sh);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             __hip_atomic_store(&ctl->share[parity ^ 1], sh.share_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the next launch's join word (the launch that used it last has ended)
+            __hip_atomic_store(&ctl->join[parity ^ 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (!share) {
             if (sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
             return;
@@ -1095,7 +1175,12 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         if (sh.map_req && (int)threadIdx.x < B.nb)
             ctl->margin[threadIdx.x] = (unsigned long long)__double_as_longlong(1e300);
     }
-    if (!box_barrier(ctl, sh, Bg)) return;
+    // the first workgroup maps alone when nothing is to be mapped, or, with
+    // coop == 2 (a test of this path), always
+    if (!join_remap(ctl, sh, parity, lead, lead && (!sh.map_req || coop == 2))) {
+        if (lead && sh.map_req) remap_box<S>(B, Bg, sh, qm, mg);
+        return;
+    }
     if (threadIdx.x == 0) {
         sh.map_req = __hip_atomic_load(&ctl->map_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sh.cur = __hip_atomic_load(&ctl->cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

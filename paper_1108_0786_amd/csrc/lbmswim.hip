@@ -68,7 +68,7 @@ struct lbm_ctx {
     std::vector<int> active_host;
     bool work_dirty = true;
     bool force_map = false;
-    bool coop_remap = true;        // share the mapping among a box's coupling workgroups
+    int coop_remap = 1;            // share the mapping among a box's coupling workgroups (2: join, map alone)
     bool aa = false;               // stream in place (one buffer, layout by step parity)
     bool flow_any = false;         // some box samples the time-averaged flow
     bool force_any = false;        // some box has the test-only body force
@@ -434,7 +434,7 @@ int launch_couple(lbm_ctx *c, const int *active_dev, int nactive, int mode) {
     return dispatch_storage(c->storage, [&](auto *tag) -> int {
         using S = std::remove_pointer_t<decltype(tag)>;
         // cooperative only if every workgroup of the launch is resident at once
-        const int coop = c->coop_remap && nactive * kRedBlocks <= c->coop_blocks ? 1 : 0;
+        const int coop = c->coop_remap && nactive * kRedBlocks <= c->coop_blocks ? c->coop_remap : 0;
         hipLaunchKernelGGL(couple_kernel<S>, dim3(nactive * kRedBlocks), dim3(kCoupleThreads), 0, c->stream,
                            c->d_boxes, active_dev, c->d_qmaps, c->d_margins, mode, c->force_map ? 1 : 0, coop);
         hipError_t e = hipGetLastError();
@@ -1628,8 +1628,8 @@ int lbm_tune(lbm_ctx *c, int32_t key, int64_t value) {
             c->force_map = value != 0;
             break;
         case LBM_TUNE_COOP_REMAP:
-            if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "cooperative remap is 0 or 1");
-            c->coop_remap = value != 0;
+            if (value < 0 || value > 2) return fail(c, LBM_E_ARG, "cooperative remap is 0, 1 or 2");
+            c->coop_remap = (int)value;
             break;
         case LBM_TUNE_STREAMING:
             if (value != 0 && value != 1) return fail(c, LBM_E_ARG, "streaming is 0 (two buffers) or 1 (in place)");

@@ -99,3 +99,23 @@ def test_batched_boxes_against_oracle(sweep_oracle, storage, tol):
         assert np.array_equal(batch.flags(b) & 0x7F, flags), c.name
         assert eF < tol and eD < tol and eV < tol and eP < tol, c.name
     batch.close()
+
+
+@pytest.mark.parametrize("coop", [1, 2])
+def test_shared_mapping_in_a_batch_bitwise(coop):
+    # eight boxes whose bodies remap, each with its own join words: the shared
+    # mapping (1) and its fallback with the workgroups joined (2) give the
+    # one-workgroup mapping's results bit for bit
+    from paper_1108_0786_amd.sim import BatchSim
+    steps = 60
+    cases = [W.forced_motion(steps=steps) for _ in range(8)]
+    print(f"[gpu] shared mapping in a batch of {len(cases)}, coop {coop}", flush=True)
+    out = []
+    for c in (0, coop):
+        b = BatchSim(cases, storage="f64", traj_cap=steps, tune={"coop_remap": c})
+        b.step(steps)
+        b.status()
+        out.append([(b.populations(i), b.trajectory(i), b.flags(i)) for i in range(len(cases))])
+        b.close()
+    for (p0, t0, f0), (p1, t1, f1) in zip(*out):
+        assert np.array_equal(p0, p1) and np.array_equal(t0, t1) and np.array_equal(f0, f1)

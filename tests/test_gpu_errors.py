@@ -101,7 +101,7 @@ def test_calls_in_the_wrong_state():
     sim.flow_average_begin(0)
     assert lib.lbm_tune(sim.ctx, 99, 1) == abi.LBM_E_ARG
     assert lib.lbm_tune(sim.ctx, abi.TUNE["block"], 100) == abi.LBM_E_ARG
-    assert lib.lbm_tune(sim.ctx, abi.TUNE["coop_remap"], 2) == abi.LBM_E_ARG
+    assert lib.lbm_tune(sim.ctx, abi.TUNE["coop_remap"], 3) == abi.LBM_E_ARG
     assert lib.lbm_step(sim.ctx, -1) == abi.LBM_E_ARG
     sim.step(5)
     sim.status()

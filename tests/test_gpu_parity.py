@@ -186,12 +186,13 @@ def test_overlapping_bodies_rejected():
 
 @pytest.mark.parametrize("tune", [{"graph_steps": 0}, {"graph_steps": 7}, {"block": 128, "xcd_order": 0},
                                   {"xcd_order": 1}, {"block": 512}, {"full_remap": 1}, {"nontemporal": 1},
-                                  {"coop_remap": 0}])
+                                  {"coop_remap": 0}, {"coop_remap": 2}])
 def test_launch_options_are_bitwise_identical(tune):
     # graphs, tile sizes, tile order, the remap skip and the mapping by one or
     # by all of a box's workgroups change nothing: the reductions are in fixed
     # order, the skip only omits no-op remaps, and the shared mapping numbers
-    # the links in the same cell order
+    # the links in the same cell order.  coop_remap 2 takes the fallback of
+    # the shared mapping: the workgroups join, and the first maps alone
     case = W.forced_motion(steps=60)
     print(f"[gpu] launch options {tune}", flush=True)
     ref = _sim(case, storage="f64", traj_cap=60)

@@ -42,7 +42,7 @@ def _same(a, b, steps):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
-@pytest.mark.parametrize("coop", [0, 1])
+@pytest.mark.parametrize("coop", [0, 1, 2])
 def test_in_place_matches_two_buffer_bitwise(storage, coop):
     # a kinematic sphere dragged across about a dozen cells: cells change
     # side at even and at odd steps
