@@ -1118,21 +1118,28 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
     // first workgroup writes the next launch's hint while others of this
     // launch may still be about to read theirs.
     // One thread per workgroup counts and reads; the whole workgroup must
-    // take the same decision.
-    if (threadIdx.x == 0) {
-        // both hints are read while the count is in flight
-        const int h0 = __hip_atomic_load(&ctl->share[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int h1 = __hip_atomic_load(&ctl->share[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrival =
-            __hip_atomic_fetch_add(&ctl->launches, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sh.parity = (int)((arrival / kRedBlocks) & 1u);
-        sh.hint = sh.parity ? h1 : h0;
-    }
-    __syncthreads();
-    const int parity = sh.parity;
-    const bool share = coop && (mode == kModeMapOnly || force_map || sh.hint != 0);
+    // take the same decision.  The other workgroups need the answer at once
+    // (they stay only for a shared remap); the first one only after the step,
+    // so there the count is taken by a thread of the last wave and stays in
+    // flight while the workgroup stages the tables and sums the records.
     const bool lead = r == 0;
-    if (!share && !lead) return;
+    const int counter = lead ? kCoupleThreads - 64 : 0;
+    int h0 = 0, h1 = 0;
+    unsigned arrival = 0u;
+    if ((int)threadIdx.x == counter) {
+        // both hints are read while the count is in flight
+        h0 = __hip_atomic_load(&ctl->share[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        h1 = __hip_atomic_load(&ctl->share[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        arrival = __hip_atomic_fetch_add(&ctl->launches, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!lead) {
+        if (threadIdx.x == 0) {
+            sh.parity = (int)((arrival / kRedBlocks) & 1u);
+            sh.hint = sh.parity ? h1 : h0;
+        }
+        __syncthreads();
+        if (!(coop && (mode == kModeMapOnly || force_map || sh.hint != 0))) return;
+    }
     if (lead) {
         if (threadIdx.x == 0) {
             sh.cur = B.cur;
@@ -1150,8 +1157,16 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         }
     }
     if (lead) {
+        if ((int)threadIdx.x == counter) {
+            sh.parity = (int)((arrival / kRedBlocks) & 1u);
+            sh.hint = sh.parity ? h1 : h0;
+        }
         if (threadIdx.x < 64) decide_map(B, Bg, sh, force_map || mode == kModeMapOnly);
-        stage_out(B, sh);
+        stage_out(B, sh);   // begins with a barrier: sh.parity and sh.hint are set
+    }
+    const int parity = sh.parity;
+    const bool share = coop && (mode == kModeMapOnly || force_map || sh.hint != 0);
+    if (lead) {
         if (threadIdx.x == 0) {
             __hip_atomic_store(&ctl->share[parity ^ 1], sh.share_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // the next launch's join word (the launch that used it last has ended)
