@@ -170,7 +170,9 @@ __device__ __forceinline__ void sum_records(const BoxDesc &B, CoupleShared &sh) 
 // Force and torque of every body: the deviation sums plus the geometric
 // part, G = (integer sum) / 36 and its torque S / 72 - f x G, f the
 // fractional part of the body position (lever arms are taken from the cell
-// R = floor(X)).  Needs the body table in LDS and sum_records done.
+// R = floor(X)).  Needs the body table in LDS and sum_records done; thread
+// b finishes body b (no barrier: rigid_step runs it beside the driving and
+// spring forces).
 __device__ __forceinline__ void finish_forces(const BoxDesc &B, CoupleShared &sh) {
     const int b = threadIdx.x;
     if (b < B.nb) {
@@ -190,38 +192,42 @@ __device__ __forceinline__ void finish_forces(const BoxDesc &B, CoupleShared &sh
             sh.T[b][v] = sh.psum[b][3 + v] + Tg[v];
         }
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // 2. rigid bodies
 // ---------------------------------------------------------------------------
 // B is the kernel's snapshot of the box descriptor (read only); the step
-// counter, buffer index and status go to the descriptor itself, Bg.
+// counter, buffer index and status go to the descriptor itself, Bg.  With
+// FLUID the first wave finishes the hydrodynamic force and torque of every
+// body (finish_forces) while the other three waves evaluate the driving and
+// spring forces; without it (the swimmer in vacuum) sh.F and sh.T are zero.
+template <bool FLUID>
 __device__ __forceinline__ void rigid_step(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh) {
     const int nb = B.nb;
     const long long n = B.step;
     const int t = threadIdx.x;
+    if (FLUID && t < 64) finish_forces(B, sh);
     // driving, Eqs. FB1-FB3 (delayed right force): the left force of drive d
-    // by thread d of the first wave, the right force by thread d of the
-    // second, so that the two sines are evaluated side by side
-    if (t < B.nd) {
-        const DevDrive &dv = sh.drive[t];
+    // by thread d of the second wave, the right force by thread d of the
+    // third, so that the two sines are evaluated side by side
+    if (t >= 64 && t - 64 < B.nd) {
+        const DevDrive &dv = sh.drive[t - 64];
         const double om = 2.0 * M_PI / dv.period;
         double fl = -dv.amplitude * sin(om * (double)n);
         if (dv.off_left >= 0 && n >= dv.off_left) fl = 0.0;
-        sh.drv[t][0] = fl;
-    } else if (t >= 64 && t - 64 < B.nd) {
-        const DevDrive &dv = sh.drive[t - 64];
+        sh.drv[t - 64][0] = fl;
+    } else if (t >= 128 && t - 128 < B.nd) {
+        const DevDrive &dv = sh.drive[t - 128];
         const double om = 2.0 * M_PI / dv.period;
         double fr = dv.amplitude * sin(om * (double)n - dv.phase_lag);
         if (dv.gate && om * (double)n < dv.phase_lag) fr = 0.0;
         if (dv.off_right >= 0 && n >= dv.off_right) fr = 0.0;
-        sh.drv[t - 64][1] = fr;
+        sh.drv[t - 128][1] = fr;
     }
     // springs, Eqs. spring_i, damp_i, osci_i/j: one thread per spring, in the
-    // third wave
-    const int e = t - 128;
+    // fourth wave
+    const int e = t - 192;
     if (e >= 0 && e < B.ns) {
         const DevSpring &sp = sh.spring[e];
         const DevBody &bi = sh.body[sp.i];
@@ -1152,8 +1158,7 @@ __global__ __launch_bounds__(kCoupleThreads) void couple_kernel(BoxDesc *boxes, 
         if (mode == kModeStep) sum_records(B, sh);
         stage_store(B, sh, qm, mg, st);
         if (mode == kModeStep) {
-            finish_forces(B, sh);
-            rigid_step(B, Bg, sh);
+            rigid_step<true>(B, Bg, sh);
         }
     }
     if (lead) {
@@ -1230,7 +1235,7 @@ __global__ __launch_bounds__(kCoupleThreads) void vacuum_kernel(BoxDesc *systems
     if (threadIdx.x == 0) sh.cur = B.cur;
     __syncthreads();
     for (long long s = 0; s < nsteps; ++s) {
-        rigid_step(B, Bg, sh);
+        rigid_step<false>(B, Bg, sh);
         B.step += 1;
     }
     stage_out(B, sh);
