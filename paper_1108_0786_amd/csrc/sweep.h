@@ -349,6 +349,35 @@ struct PushFast<S, 19> {
                                                const typename Storage<S>::C *, float) {}
 };
 
+// Push of a cell on a wall away from bodies: as PushFast, except that a
+// population that would leave through a wall is bounced back into slot
+// opp(A) of the cell itself (Eq. lbm:bounce_back).  lo_w / hi_w: bit a set
+// if the cell is at the low / high end of axis a and that axis has walls.
+template <typename S, int A>
+struct PushWall {
+    template <typename P>
+    static __device__ __forceinline__ void run(P dst, long long stride, int cell, const int *off_p,
+                                               const int *off_m, unsigned lo_w, unsigned hi_w,
+                                               const typename Storage<S>::C *f, float scale) {
+        const bool out = (ex(A) > 0 ? (hi_w & 1u) : ex(A) < 0 ? (lo_w & 1u) : 0u) ||
+                         (ey(A) > 0 ? (hi_w & 2u) : ey(A) < 0 ? (lo_w & 2u) : 0u) ||
+                         (ez(A) > 0 ? (hi_w & 4u) : ez(A) < 0 ? (lo_w & 4u) : 0u);
+        const int o = (ex(A) > 0 ? off_p[0] : ex(A) < 0 ? off_m[0] : 0) +
+                      (ey(A) > 0 ? off_p[1] : ey(A) < 0 ? off_m[1] : 0) +
+                      (ez(A) > 0 ? off_p[2] : ez(A) < 0 ? off_m[2] : 0);
+        const size_t at = out ? (size_t)opp(A) * stride + (size_t)cell
+                              : (size_t)A * stride + (size_t)(unsigned)(cell + o);
+        Storage<S>::store(dst, at, f[A], scale);
+        PushWall<S, A + 1>::run(dst, stride, cell, off_p, off_m, lo_w, hi_w, f, scale);
+    }
+};
+template <typename S>
+struct PushWall<S, 19> {
+    template <typename P>
+    static __device__ __forceinline__ void run(P, long long, int, const int *, const int *, unsigned, unsigned,
+                                               const typename Storage<S>::C *, float) {}
+};
+
 // Interior pushes with the x-shifted directions realigned across lanes.
 // The cells of a wave are consecutive, so the push of lane l along +x lands
 // on lane l+1's cell: if lane l+1 holds the next cell of the same row, lane
@@ -494,7 +523,18 @@ void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
     const bool near = general && (fl & kNearBit);
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);
     int lfirst = 0x7fffffff, lend = -1;   // this cell's links
-    if (general) {
+    if (general && !near) {
+        // on a wall, away from bodies
+        unsigned lo_w = 0u, hi_w = 0u;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool w = !((per >> a) & 1);
+            lo_w |= (w && at_lo[a]) ? 1u << a : 0u;
+            hi_w |= (w && at_hi[a]) ? 1u << a : 0u;
+        }
+        St::store(dst, (size_t)cell, f[0], B.scale);
+        PushWall<S, 1>::run(dst, stride, cell, off_p, off_m, lo_w, hi_w, f, B.scale);
+    } else if (general) {
         St::store(gdst, (size_t)cell, f[0], B.scale);
         Owners owner;
         int slot = 0;

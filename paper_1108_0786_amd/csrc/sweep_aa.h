@@ -97,6 +97,40 @@ struct PullFast<S, NT, 19> {
                                                typename Storage<S>::C *, float) {}
 };
 
+// Odd step, cell on a wall away from bodies: as PullFast, except that a
+// population whose source x - e_A lies beyond a wall was reflected by x
+// itself into slot A of x.  lo_w / hi_w: bit a set if the cell is at the
+// low / high end of axis a and that axis has walls.
+template <int A>
+__device__ __forceinline__ bool beyond_wall(unsigned lo_w, unsigned hi_w) {
+    return (ex(A) > 0 ? (hi_w & 1u) : ex(A) < 0 ? (lo_w & 1u) : 0u) ||
+           (ey(A) > 0 ? (hi_w & 2u) : ey(A) < 0 ? (lo_w & 2u) : 0u) ||
+           (ez(A) > 0 ? (hi_w & 4u) : ez(A) < 0 ? (lo_w & 4u) : 0u);
+}
+
+template <typename S, bool NT, int A>
+struct PullWall {
+    template <typename P>
+    static __device__ __forceinline__ void run(P src, long long stride, int cell, const int *off_p,
+                                               const int *off_m, unsigned lo_w, unsigned hi_w,
+                                               typename Storage<S>::C *f, float inv_scale) {
+        const int o = (ex(A) > 0 ? off_m[0] : ex(A) < 0 ? off_p[0] : 0) +
+                      (ey(A) > 0 ? off_m[1] : ey(A) < 0 ? off_p[1] : 0) +
+                      (ez(A) > 0 ? off_m[2] : ez(A) < 0 ? off_p[2] : 0);
+        // x - e_A beyond a wall: x + e_opp(A) is
+        const size_t at = beyond_wall<opp(A)>(lo_w, hi_w) ? (size_t)A * stride + (size_t)cell
+                                                          : (size_t)opp(A) * stride + (size_t)(unsigned)(cell + o);
+        f[A] = Storage<S>::template load<NT>(src, at, inv_scale);
+        PullWall<S, NT, A + 1>::run(src, stride, cell, off_p, off_m, lo_w, hi_w, f, inv_scale);
+    }
+};
+template <typename S, bool NT>
+struct PullWall<S, NT, 19> {
+    template <typename P>
+    static __device__ __forceinline__ void run(P, long long, int, const int *, const int *, unsigned, unsigned,
+                                               typename Storage<S>::C *, float) {}
+};
+
 // Even step, cell next to a body: f*_A(x) to slot opp(A) of x, with the
 // moving-wall term and the link's record where x + e_A is a body cell.
 template <typename S, int A>
@@ -185,7 +219,14 @@ void sweep_aa_kernel(BoxDesc *boxes, const WorkItem *work, int nwork, int xcd_or
     }
     const bool near = fluid && (fl & kNearBit);
     const bool fast = fluid && !wall && !near;
-    const bool general = fluid && !fast;
+    const bool at_wall = fluid && wall && !near;
+    unsigned lo_w = 0u, hi_w = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool w = !((per >> a) & 1);
+        lo_w |= (w && at_lo[a]) ? 1u << a : 0u;
+        hi_w |= (w && at_hi[a]) ? 1u << a : 0u;
+    }
     Owners owner;
     int slot = 0, lfirst = 0x7fffffff, lend = -1;
     if (near) {
@@ -204,7 +245,10 @@ void sweep_aa_kernel(BoxDesc *boxes, const WorkItem *work, int nwork, int xcd_or
     } else if (fast) {
         f[0] = St::template load<NT>(pop, (size_t)cell, B.inv_scale);
         PullFast<S, NT, 1>::run(pop, stride, cell, off_p, off_m, f, B.inv_scale);
-    } else if (general) {
+    } else if (at_wall) {
+        f[0] = St::template load<NT>(pop, (size_t)cell, B.inv_scale);
+        PullWall<S, NT, 1>::run(pop, stride, cell, off_p, off_m, lo_w, hi_w, f, B.inv_scale);
+    } else if (near) {
         f[0] = St::load(pop, (size_t)cell, B.inv_scale);
         PullAll<S, 1>::run(B, pop, stride, cell, i, j, k, owner, f);
     }
@@ -226,7 +270,10 @@ void sweep_aa_kernel(BoxDesc *boxes, const WorkItem *work, int nwork, int xcd_or
     } else if (fast) {
         St::store(pop, (size_t)cell, f[0], B.scale);
         PushFast<S, 1>::run(pop, stride, cell, off_p, off_m, f, B.scale);
-    } else if (general) {
+    } else if (at_wall) {
+        St::store(pop, (size_t)cell, f[0], B.scale);
+        PushWall<S, 1>::run(pop, stride, cell, off_p, off_m, lo_w, hi_w, f, B.scale);
+    } else if (near) {
         St::store(pop, (size_t)cell, f[0], B.scale);
         PushAll<S, 1>::run(B, (S *)pop, stride, cell, i, j, k, owner, f, rho, slot);
     }
