@@ -383,8 +383,8 @@ struct PushWall<S, 19> {
 // on lane l+1's cell: if lane l+1 holds the next cell of the same row, lane
 // l+1 stores the value it received from lane l at its own, aligned slot
 // (from_left); lane l stores it itself only where no neighbour takes it
-// (own_px), that is at the end of a row or a wave or next to a cell on the
-// general path.  -x works the same way from the right.  Every destination is
+// (own_px), that is at the end of a row or a wave or next to a wall or
+// near-body cell.  -x works the same way from the right.  Every destination is
 // still written exactly once, with the same value.
 struct XLanes {
     bool from_left, from_right, own_px, own_mx, fast;
@@ -517,8 +517,9 @@ void sweep_kernel(BoxDesc *boxes, const WorkItem *work, int nwork,
             PushFast<S, 1>::run(dst, stride, cell, off_p, off_m, f, B.scale);
         }
     }
-    // cells on the general path: walls and near-body cells.  Every lane stays
-    // for the wave's momentum-exchange sums.
+    // the other fluid cells: on a wall (PushWall) or next to a body (the
+    // general path, PushAll).  Every lane stays for the wave's
+    // momentum-exchange sums.
     const bool general = valid && fluid && !fast;
     const bool near = general && (fl & kNearBit);
     S *gdst = (S *)(B.cur ? B.pop0 : B.pop1);

@@ -53,7 +53,7 @@ __device__ __forceinline__ size_t current_slot(const BoxDesc &B, bool swapped, i
     return (size_t)b * stride + (size_t)cell;
 }
 
-// Odd step, cell on the general path: pull f_b(x) for b = A..18.
+// Odd step, cell next to a body (the general path): pull f_b(x) for b = A..18.
 template <typename S, int A>
 struct PullAll {
     template <typename P>
