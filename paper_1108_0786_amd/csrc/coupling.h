@@ -785,35 +785,57 @@ __device__ __forceinline__ int map_links(const BoxDesc &B, CoupleShared &sh, con
 __device__ __forceinline__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int L) {
     const int chunk = (L + kCoupleThreads - 1) / kCoupleThreads;
     const int l0 = min((int)threadIdx.x * chunk, L), l1 = min(l0 + chunk, L);
+    // The link lists were written by other workgroups just before: every
+    // read misses the workgroup's caches, so the loops below read eight
+    // links at a time, with the loads in flight together.
+    // Bodies with links in wave w, from its first link l on.
     auto wave_mask = [&](int l, int w) {
         unsigned m = 0;
-        for (int q = l; q < L && (B.link_cell[q] >> 6) == w; ++q) m |= 1u << B.link_body[q];
+        for (int q = l; q < L; q += 8) {
+            int cw[8], bd[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cw[u] = q + u < L ? B.link_cell[q + u] >> 6 : -1;
+                bd[u] = q + u < L ? B.link_body[q + u] : 0;
+            }
+            bool end = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                end = end || cw[u] != w;
+                if (!end) m |= 1u << bd[u];
+            }
+            if (end) break;
+        }
         return m;
     };
-    auto starts_wave = [&](int l, int w) { return l == 0 || (B.link_cell[l - 1] >> 6) != w; };
+    // Calls f(l, w) for every link l of [l0, l1) that starts wave w.
+    auto for_starts = [&](auto f) {
+        int prev = l0 > 0 ? B.link_cell[l0 - 1] >> 6 : -1;
+        for (int q = l0; q < l1; q += 8) {
+            int cw[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cw[u] = q + u < l1 ? B.link_cell[q + u] >> 6 : -1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (q + u < l1 && cw[u] != prev) f(q + u, cw[u]);
+                prev = cw[u];
+            }
+        }
+    };
     // records of each body among the waves that start in this thread's range
     unsigned seen = 0;   // bodies with a record here
-    for (int l = l0; l < l1; ++l) {
-        const int w = B.link_cell[l] >> 6;
-        if (starts_wave(l, w)) seen |= wave_mask(l, w);
-    }
+    for_starts([&](int l, int w) { seen |= wave_mask(l, w); });
     int off = 0;   // records of the bodies before b
     for (int b = 0; b < B.nb; ++b) {
         int mine = 0;
-        if (seen & (1u << b))
-            for (int l = l0; l < l1; ++l) {
-                const int w = B.link_cell[l] >> 6;
-                if (starts_wave(l, w)) mine += (wave_mask(l, w) >> b) & 1u;
-            }
+        if (seen & (1u << b)) for_starts([&](int l, int w) { mine += (wave_mask(l, w) >> b) & 1u; });
         int total;
         int next = off + block_scan(mine, &total, sh);
         if (seen & (1u << b))
-            for (int l = l0; l < l1; ++l) {
-                const int w = B.link_cell[l] >> 6;
-                if (!starts_wave(l, w)) continue;
+            for_starts([&](int l, int w) {
                 const unsigned m = wave_mask(l, w);
                 if ((m >> b) & 1u) B.grp_pos[l + __popc(m & ((1u << b) - 1u))] = next++;
-            }
+            });
         if (threadIdx.x == 0) Bg.rec_off[b] = off;
         off += total;
     }
