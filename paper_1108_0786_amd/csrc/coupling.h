@@ -783,33 +783,14 @@ __device__ __forceinline__ int map_links(const BoxDesc &B, CoupleShared &sh, con
 // waves that start in it; one block scan per body numbers the records.
 // Needs the whole link list written.
 __device__ __forceinline__ void map_groups(const BoxDesc &B, BoxDesc &Bg, CoupleShared &sh, int L) {
+    const int t = (int)threadIdx.x;
     const int chunk = (L + kCoupleThreads - 1) / kCoupleThreads;
-    const int l0 = min((int)threadIdx.x * chunk, L), l1 = min(l0 + chunk, L);
-    // The link lists were written by other workgroups just before: every
-    // read misses the workgroup's caches, so the loops below read eight
-    // links at a time, with the loads in flight together.
-    // Bodies with links in wave w, from its first link l on.
-    auto wave_mask = [&](int l, int w) {
-        unsigned m = 0;
-        for (int q = l; q < L; q += 8) {
-            int cw[8], bd[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                cw[u] = q + u < L ? B.link_cell[q + u] >> 6 : -1;
-                bd[u] = q + u < L ? B.link_body[q + u] : 0;
-            }
-            bool end = false;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                end = end || cw[u] != w;
-                if (!end) m |= 1u << bd[u];
-            }
-            if (end) break;
-        }
-        return m;
-    };
-    // Calls f(l, w) for every link l of [l0, l1) that starts wave w.
-    auto for_starts = [&](auto f) {
+    const int l0 = min(t * chunk, L), l1 = min(l0 + chunk, L);
+    // The link lists were written by other workgroups just before, so the
+    // loops read eight links at a time, with the loads in flight together.
+    // Calls f(l, w) for every link l of [l0, l1), w its wave, and whether it
+    // starts its wave.
+    auto for_links = [&](auto f) {
         int prev = l0 > 0 ? B.link_cell[l0 - 1] >> 6 : -1;
         for (int q = l0; q < l1; q += 8) {
             int cw[8];
@@ -817,23 +798,73 @@ __device__ __forceinline__ void map_groups(const BoxDesc &B, BoxDesc &Bg, Couple
             for (int u = 0; u < 8; ++u) cw[u] = q + u < l1 ? B.link_cell[q + u] >> 6 : -1;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                if (q + u < l1 && cw[u] != prev) f(q + u, cw[u]);
+                if (q + u < l1) f(q + u, cw[u], cw[u] != prev);
                 prev = cw[u];
             }
         }
     };
-    // records of each body among the waves that start in this thread's range
+    // 1. Every thread ORs the bodies of its links run by run (a run: the links
+    // of one wave within the thread's range).  The mask of a run that starts
+    // its wave goes to the wave's first link in the scratch words (the link
+    // records are free during a mapping); the first run, if it continues a
+    // wave from the threads before, is published in the LDS (hw, hm) for the
+    // thread that holds the wave's start, with whether it fills the range.
+    unsigned *wmask = (unsigned *)B.link_rec;
+    int *hw = sh.rlist;                      // wave of the first run, -1 if none
+    unsigned *hm = (unsigned *)sh.red;       // its mask; [kCoupleThreads + t]: it fills the range
+    int run_start = -1, run_w = -1, first_w = -1;
+    unsigned run_m = 0u, first_m = 0u;
+    bool first_open = true;                  // still in the first run
+    for_links([&](int l, int w, bool starts) {
+        if (l > l0 && w != run_w) {          // a run ends
+            if (run_start >= 0) wmask[run_start] = run_m;
+            else if (first_open) first_m = run_m;
+            first_open = false;
+            run_m = 0u;
+            run_start = -1;
+        }
+        if (l == l0) first_w = starts ? -1 : w;
+        if (starts) run_start = l;
+        run_w = w;
+        run_m |= 1u << B.link_body[l];
+    });
+    const bool open_end = l1 > l0 && run_start >= 0;   // the last run starts a wave that may go on
+    if (l1 > l0 && run_start < 0 && first_open) first_m = run_m;
+    hw[t] = first_w;
+    hm[t] = first_m;
+    hm[kCoupleThreads + t] = (l1 > l0 && first_open && first_w >= 0) ? 1u : 0u;
+    __syncthreads();
+    // 2. The last run of a thread may start a wave that the next threads go on
+    // with: add their first runs while they belong to it.
+    if (open_end) {
+        unsigned m = run_m;
+        for (int k = t + 1; k < kCoupleThreads && hw[k] == run_w; ++k) {
+            m |= hm[k];
+            if (!hm[kCoupleThreads + k]) break;
+        }
+        wmask[run_start] = m;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // 3. Number the records body by body, in the order of the waves: one block
+    // scan per body; the q-th body of a wave takes the wave's slot l + q.
     unsigned seen = 0;   // bodies with a record here
-    for_starts([&](int l, int w) { seen |= wave_mask(l, w); });
+    for_links([&](int l, int, bool starts) {
+        if (starts) seen |= wmask[l];
+    });
     int off = 0;   // records of the bodies before b
     for (int b = 0; b < B.nb; ++b) {
         int mine = 0;
-        if (seen & (1u << b)) for_starts([&](int l, int w) { mine += (wave_mask(l, w) >> b) & 1u; });
+        if (seen & (1u << b))
+            for_links([&](int l, int, bool starts) {
+                if (starts) mine += (wmask[l] >> b) & 1u;
+            });
         int total;
         int next = off + block_scan(mine, &total, sh);
         if (seen & (1u << b))
-            for_starts([&](int l, int w) {
-                const unsigned m = wave_mask(l, w);
+            for_links([&](int l, int, bool starts) {
+                if (!starts) return;
+                const unsigned m = wmask[l];
                 if ((m >> b) & 1u) B.grp_pos[l + __popc(m & ((1u << b) - 1u))] = next++;
             });
         if (threadIdx.x == 0) Bg.rec_off[b] = off;
